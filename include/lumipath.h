@@ -1,0 +1,186 @@
+/*
+ * lumipath.h -- C ABI of the MI355X light-field library (liblumipath.so).
+ *
+ * Implements the data-parallel path of Fink et al., "LumiPath -- Towards
+ * Real-time Physically-based Rendering on Embedded Devices" (arXiv
+ * 1903.03837): the precomputed light field Lhat(i,j) over two spherical-
+ * Fibonacci point sets on a sphere S bounding the scene (Sec. 2, Fig. 1), and
+ * image synthesis by looking up and blending its texels (Sec. 2, Fig. 2).
+ * The scene is a scalar density volume under a transfer function and a light,
+ * path traced volumetrically (the paper renders surfaces; Sec. 4 names
+ * volumes as the goal).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is device memory owned by the caller unless marked
+ *    "host".  Structs passed by pointer are host memory, read during the call
+ *    only.  The library allocates nothing and keeps no state between calls
+ *    apart from the thread-local error message.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    asynchronous and stream-ordered; the caller keeps buffers alive until
+ *    the stream has passed the call.
+ *  - Return value: LF_OK (0) or a negative lf_status.  Arguments are checked
+ *    on the host before any GPU work; on error nothing is launched and
+ *    lf_last_error() describes the problem.  HIP launch failures return
+ *    LF_E_HIP with the HIP message.
+ *  - Light fields are row-major [M][N][3] RGB: texel (i, j) for origin i of
+ *    P_o (M points) and direction j of P_d (N points), stored as binary32,
+ *    binary16 or bfloat16 (round to nearest even from the FP32 mean).
+ */
+#ifndef LUMIPATH_H
+#define LUMIPATH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LUMIPATH_VERSION 1
+
+typedef enum {
+    LF_OK = 0,
+    LF_E_ARG = -1,          /* bad pointer, size, enum or geometry */
+    LF_E_RANGE = -2,        /* sizes beyond the supported range */
+    LF_E_UNSUPPORTED = -3,  /* valid but not implemented combination */
+    LF_E_WORKSPACE = -4,    /* workspace missing or too small */
+    LF_E_HIP = -5           /* HIP runtime error */
+} lf_status;
+
+enum { LF_F32 = 0, LF_F16 = 1, LF_BF16 = 2 };           /* light-field storage */
+enum { LF_VOX_U8 = 0, LF_VOX_U16 = 1, LF_VOX_F32 = 2 };   /* voxel types */
+enum { LF_LIGHT_DIRECTIONAL = 0, LF_LIGHT_AREA = 1 };
+enum { LF_LOOKUP_FORWARD = 0, LF_LOOKUP_ADJOINT = 1 };
+
+/* Scalar volume filling the box [box_min, box_max] (inside S).  Voxel centres
+ * sit at box_min + (idx + 0.5) * extent / n; values are interpolated
+ * trilinearly (edge-clamped) and mapped through the window [vmin, vmax] onto
+ * the transfer function.  brick = 0: x-fastest linear array; brick = 8: 8^3
+ * bricks, bricks ordered x-fastest, voxels x-fastest inside a brick (each of
+ * nx, ny, nz divisible by 8).  nx, ny, nz >= 2. */
+typedef struct {
+    const void* data;       /* device [nx*ny*nz] of the voxel type */
+    int32_t type;           /* LF_VOX_* */
+    int32_t nx, ny, nz;
+    int32_t brick;          /* 0 or 8 */
+    float vmin, vmax;       /* vmax > vmin */
+    float box_min[3], box_max[3];
+} lf_volume;
+
+/* Transfer function: lut_size RGBA entries (device, float32 [lut_size][4]),
+ * interpolated linearly; sigma_t = density_scale * alpha, single-scattering
+ * albedo = rgb clamped to [0,1].  2 <= lut_size <= 1024. */
+typedef struct {
+    const float* lut;
+    int32_t lut_size;
+    float density_scale;    /* >= 0 */
+} lf_medium;
+
+/* One light plus a constant environment radiance `env` seen by paths that
+ * leave the volume.  Directional: unit `dir` towards the light, `radiance`
+ * is its irradiance.  Area: parallelogram corner + s e1 + t e2 (s,t in
+ * [0,1]), emitting `radiance` on the side cross(e1, e2) points to; it must
+ * lie outside the volume box. */
+typedef struct {
+    int32_t kind;           /* LF_LIGHT_* */
+    float dir[3];
+    float corner[3], e1[3], e2[3];
+    float radiance[3];
+    float env[3];
+} lf_light;
+
+/* Ray set and path-tracer settings (Sec. 2: S with centre O = center and
+ * radius R = radius; P_o of M points, P_d of N points; ray k = i*N + j runs
+ * from O + R p_i towards O + R p_j with its origin jittered on the disk of
+ * area 4 pi R^2 / M when jitter != 0).  M, N in [1, 65535], M*N < 2^32.
+ * spp >= 1 samples, 1 <= max_bounces <= 65535 scatter vertices, |hg_g| < 1.
+ * majorant <= 0 selects 1.25 * density_scale * max alpha of the sampling
+ * medium.  Rows [row_begin, row_end) of i are generated (row_end <= 0: M);
+ * results do not depend on this split.  stats: NULL or device uint64[4]
+ * incremented by [tentative collisions, shadow-ray steps, real collisions,
+ * path samples]. */
+typedef struct {
+    int32_t M, N;
+    float center[3];
+    float radius;
+    int32_t spp, max_bounces;
+    float hg_g;
+    float majorant;
+    uint64_t seed;
+    int32_t jitter;
+    int32_t reserved;
+    int64_t row_begin, row_end;
+    uint64_t* stats;
+} lf_gen_params;
+
+/* Pinhole view (host array): pixel (x, y) looks through its centre, row 0 at
+ * the top, vertical field of view vfov radians, aspect W/H. */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float vfov;
+} lf_camera;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lf_last_error(void);
+int lf_version(void);
+
+/* Spherical-Fibonacci point set and its inverse query (Sec. 2, SF point
+ * equation; nearest-neighbour query with "up to nine neighbors" and the
+ * filter kernel of size R sqrt(4 pi / N)).
+ *   xyz_out: NULL or float [n][3], p_i for i < n (frac(i/Phi) in FP64).
+ *   query:   NULL or float [nq][3] unit vectors; then idx_out int32 [nq][K]
+ *            receives the K nearest of the candidate set i* + {0, +-F(k-1),
+ *            +-F(k), +-F(k+1), +-F(k+2)} in order of (distance, index), -1
+ *            where fewer exist, and w_out (may be NULL) float [nq][K] the
+ *            tent weights max(0, 1 - d / sqrt(4 pi / n)) (d: unit chord).
+ *            idx_out[q][0] is the nearest point.  1 <= K <= 9.
+ * n in [1, 65535]. */
+int lf_points(int32_t n, float* xyz_out, const float* query, int64_t nq, int32_t K,
+              int32_t* idx_out, float* w_out, void* stream);
+
+/* Light-field generation (Sec. 2, Fig. 1): writes Lhat(i, j) = mean over spp
+ * path samples of the radiance along ray k = i*N + j, for rows
+ * [row_begin, row_end), into lf_out ([M][N][3] of `dtype`).  Texels with
+ * M == N and i == j (no direction) are 0.  Random numbers: Philox4x32-10
+ * keyed by `seed`, counter (k, sample, bounce << 8 | purpose, block), so the
+ * result is independent of launch shape and row split.
+ *   eval:   medium evaluated.   sample: NULL, or the medium that decides
+ *   collisions (frozen sampling: the path is importance-weighted from sample
+ *   to eval; used for finite-difference checks of the adjoint).
+ *   ws / ws_bytes: when ws == NULL only *ws_bytes is set (the workspace
+ *   size); otherwise *ws_bytes must be at least that size. */
+int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sample,
+                const lf_light* light, const lf_gen_params* params, int32_t dtype, void* lf_out,
+                void* ws, size_t* ws_bytes, void* stream);
+
+/* Image synthesis from the light field (Sec. 2, Fig. 2).  For every pixel
+ * of n_views W x H views: the view ray's front and back hits on S (tangential
+ * rays discarded) are mapped to their K nearest points of P_o and P_d and the
+ * K x K texels blended with normalised tent weights (pairs i == j excluded
+ * when M == N); K = 1 is nearest sampling.  Uses M, N, center, radius of
+ * params.
+ *   mode LF_LOOKUP_FORWARD: lf (dtype) -> img float [n_views][H][W][3].
+ *   mode LF_LOOKUP_ADJOINT: img holds d(loss)/d(img); d_lf (float32
+ *        [M][N][3]) is incremented by its transpose (atomics; lf unused).
+ *   nn_out: NULL or int32 [n_views][H][W][2], nearest (i, j), -1 on a miss.
+ *   cams: host array of n_views cameras, each eye outside S. */
+int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams,
+              int32_t n_views, int32_t W, int32_t H, int32_t K, int32_t mode, float* img,
+              float* d_lf, int32_t* nn_out, void* stream);
+
+/* Adjoint of lf_generate (path-replay extension): given d_lf = d(loss)/d(Lhat)
+ * (float32 [M][N][3]), overwrites d_lut (float32 [lut_size][4]) and d_scale
+ * (float32 [1]) with d(loss)/d(LUT) and d(loss)/d(density_scale) of the
+ * estimator for the same random stream, majorant held fixed.  Each sample is
+ * traced twice (total radiance, then scores times radiance gathered after
+ * each event); nothing is stored per path.  Accumulation uses float atomics:
+ * reproducible to rounding only.  Rows with zero adjoint are skipped.
+ * Workspace as for lf_generate. */
+int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf_light* light,
+                         const lf_gen_params* params, const float* d_lf, float* d_lut,
+                         float* d_scale, void* ws, size_t* ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LUMIPATH_H */

@@ -158,15 +158,16 @@ def phantom_volume(n: int, seed: int, n_ellipsoids: int, noise: float = 20.0,
     Ellipsoid 0 is centred near the grid centre with semi-axes 0.6-0.95 of
     the half extent.  Every later ellipsoid picks a random existing parent and
     lies inside it: semi-axes 0.5-0.9 x the parent's smallest semi-axis,
-    centre offset within the remaining margin, random rotation.  HU per shell
-    uniform in [-1000, 2000], background -1000, Gaussian noise sigma = 20 HU;
+    centre offset within the remaining margin, random rotation.  HU of the
+    outer shell (the body) uniform in [-100, 300], of every inner shell
+    uniform in [-1000, 2000]; background -1000, Gaussian noise sigma = 20 HU;
     stored as clamp(round(HU + 1024), 0, 65535).  Returned (nz, ny, nx)."""
     rng = np.random.default_rng(seed)
     half = n / 2.0
     ells = []  # (centre, rotation, semi-axes, HU)
     c0 = np.full(3, half) + rng.uniform(-0.05, 0.05, 3) * n
     a0 = rng.uniform(0.6, 0.95, 3) * (half - np.abs(c0 - half).max())
-    ells.append((c0, _rotation(rng), a0, rng.uniform(-1000.0, 2000.0)))
+    ells.append((c0, _rotation(rng), a0, rng.uniform(-100.0, 300.0)))  # body: soft tissue
     for _ in range(1, n_ellipsoids):
         pc, prot, pa, _ = ells[rng.integers(len(ells))]
         a = rng.uniform(0.5, 0.9, 3) * pa.min()

@@ -187,6 +187,10 @@ double orc_uniform(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
  * (ray, sample, bounce << 8 | purpose, block) and block b supplies the
  * uniforms with stream positions 4b .. 4b+3, word by word. */
 enum { P_JITTER = 0, P_FLIGHT = 1, P_VERTEX = 2, P_SHADOW = 3 };
+/* At most 2^20 tentative collisions per free-flight or shadow segment; a
+ * segment that reaches the cap ends absorbed (free flight) or blocked
+ * (shadow).  Valid scenes never come near it. */
+#define MAX_STEPS ((int64_t)1 << 20)
 typedef struct { uint32_t key[2]; uint32_t ctr[3]; int64_t block; uint32_t words[4]; } ustream;
 
 static void us_init(ustream* u, uint64_t seed, uint32_t ray, uint32_t sample, uint32_t bounce, uint32_t purpose) {
@@ -437,7 +441,9 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
             ustream uf;
             us_init(&uf, P->seed, k, s, (uint32_t)b, P_FLIGHT);
             double t = tn;
-            for (int64_t step = 0;; ++step) {
+            int64_t step = 0;
+            for (;; ++step) {
+                if (step == MAX_STEPS) return; /* step cap: absorbed */
                 double ud = us_get(&uf, 2 * step), ua = us_get(&uf, 2 * step + 1);
                 t -= log(1.0 - ud) / sigbar;
                 if (t >= tf) break;
@@ -517,6 +523,7 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
                 us_init(&us, P->seed, k, s, (uint32_t)b, P_SHADOW);
                 double t = 0.0;
                 for (int64_t step = 0;; ++step) {
+                    if (step == MAX_STEPS) { Tr = 0.0; break; } /* step cap: blocked */
                     t -= log(1.0 - us_get(&us, step)) / sigbar;
                     if (t >= tend) break;
                     tr->stats[1] += 1.0;
@@ -814,4 +821,45 @@ void orc_lookup_adjoint(const orc_params* prm, const orc_camera* cams, int32_t W
                 for (int c = 0; c < 3; ++c) t[c] += wab[a * 9 + b] * dimg[3 * p + c];
             }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batched neighbour queries (threads over queries; each one is the plain     */
+/* brute-force query above).                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n; const double* q; int64_t q0, q1; int32_t K;
+    int64_t* idx; double* w; double* d2; double* margins; int32_t* count;
+} nb_job;
+
+static void* nb_worker(void* arg) {
+    nb_job* jb = (nb_job*)arg;
+    for (int64_t t = jb->q0; t < jb->q1; ++t) {
+        int64_t idx[9];
+        double w[9], d2[9], m[3];
+        int32_t c = orc_neighbors(jb->n, jb->q + 3 * t, jb->K, idx, w, d2, m);
+        for (int32_t a = 0; a < jb->K; ++a) {
+            jb->idx[t * jb->K + a] = a < c ? idx[a] : -1;
+            jb->w[t * jb->K + a] = a < c ? w[a] : 0.0;
+            jb->d2[t * jb->K + a] = a < c ? d2[a] : 0.0;
+        }
+        for (int a = 0; a < 3; ++a) jb->margins[3 * t + a] = m[a];
+        jb->count[t] = c;
+    }
+    return NULL;
+}
+
+void orc_neighbors_batch(int64_t n, const double* q, int64_t nq, int32_t K, int64_t* idx, double* w,
+                         double* d2, double* margins, int32_t* count, int32_t nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    nb_job* jobs = (nb_job*)calloc((size_t)nthreads, sizeof(nb_job));
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nthreads);
+    for (int32_t t = 0; t < nthreads; ++t) {
+        nb_job j = {n, q, nq * t / nthreads, nq * (t + 1) / nthreads, K, idx, w, d2, margins, count};
+        jobs[t] = j;
+        pthread_create(&th[t], NULL, nb_worker, &jobs[t]);
+    }
+    for (int32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(th);
+    free(jobs);
 }

@@ -97,6 +97,11 @@ int64_t orc_fib(int32_t k);
 int32_t orc_neighbors(int64_t n, const double q[3], int32_t K,
                       int64_t* idx, double* w, double* d2, double margins[3]);
 
+/* The same query for nq points q[3*t..] (threads over queries): idx, w, d2
+ * are [nq][K] (-1 / 0 past the count), margins [nq][3], count [nq]. */
+void orc_neighbors_batch(int64_t n, const double* q, int64_t nq, int32_t K, int64_t* idx, double* w,
+                         double* d2, double* margins, int32_t* count, int32_t nthreads);
+
 /* ---- Philox4x32-10 counter-based generator (Salmon et al., SC'11) ------
  * Pinned against rocRAND's independent implementation. */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

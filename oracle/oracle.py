@@ -75,6 +75,7 @@ def lib():
         L.orc_fib.restype = C.c_int64
         L.orc_neighbors.argtypes = [C.c_int64, P, C.c_int32, P, P, P, P]
         L.orc_neighbors.restype = C.c_int32
+        L.orc_neighbors_batch.argtypes = [C.c_int64, P, C.c_int64, C.c_int32, P, P, P, P, P, C.c_int32]
         L.orc_philox.argtypes = [P, P, P]
         L.orc_uniform.argtypes = [C.c_uint32]
         L.orc_uniform.restype = C.c_double
@@ -194,6 +195,21 @@ def neighbors(n: int, q, K: int):
     m = np.zeros(3)
     cnt = lib().orc_neighbors(n, _ptr(q), K, _ptr(idx), _ptr(w), _ptr(d2), _ptr(m))
     return idx[:cnt], w[:cnt], d2[:cnt], m
+
+
+def neighbors_batch(n: int, q, K: int, nthreads=None):
+    """Batched K-neighbour query: idx [nq,K] (-1 past the count), w, d2
+    [nq,K], margins [nq,3], count [nq]."""
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+    nq = q.shape[0]
+    idx = np.zeros((nq, K), np.int64)
+    w = np.zeros((nq, K))
+    d2 = np.zeros((nq, K))
+    m = np.zeros((nq, 3))
+    cnt = np.zeros(nq, np.int32)
+    lib().orc_neighbors_batch(n, _ptr(q), nq, K, _ptr(idx), _ptr(w), _ptr(d2), _ptr(m), _ptr(cnt),
+                              nthreads or default_threads())
+    return idx, w, d2, m, cnt
 
 
 def philox(ctr, key) -> np.ndarray:

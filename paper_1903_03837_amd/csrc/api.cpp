@@ -1,0 +1,357 @@
+// api.cpp -- the C ABI of liblumipath.so (include/lumipath.h): host-side
+// argument validation, parameter packing and kernel launches.  Validation
+// finishes before any HIP call, so a bad argument never touches the device.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lumipath.h"
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(LF_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+constexpr size_t kWorkspaceBytes = 256;
+
+int check_params(const lf_gen_params* p, bool need_rays) {
+    if (!p) return fail(LF_E_ARG, "params is NULL");
+    if (p->M < 1 || p->N < 1) return fail(LF_E_ARG, "M and N must be >= 1 (got %d, %d)", p->M, p->N);
+    if (p->M > 65535 || p->N > 65535) return fail(LF_E_RANGE, "M and N must be <= 65535");
+    if ((unsigned long long)p->M * (unsigned long long)p->N >= (1ull << 32))
+        return fail(LF_E_RANGE, "M*N must be < 2^32");
+    if (!(p->radius > 0.0f) || !std::isfinite(p->radius)) return fail(LF_E_ARG, "radius must be > 0");
+    if (!finite3(p->center)) return fail(LF_E_ARG, "center must be finite");
+    if (!need_rays) return LF_OK;
+    if (p->spp < 1) return fail(LF_E_ARG, "spp must be >= 1");
+    if (p->max_bounces < 1 || p->max_bounces > 65535) return fail(LF_E_ARG, "max_bounces must be in [1, 65535]");
+    if (!(std::fabs(p->hg_g) < 1.0f)) return fail(LF_E_ARG, "|hg_g| must be < 1");
+    if (!std::isfinite(p->majorant)) return fail(LF_E_ARG, "majorant must be finite");
+    const long long re = p->row_end <= 0 ? p->M : p->row_end;
+    if (p->row_begin < 0 || p->row_begin > re || re > p->M)
+        return fail(LF_E_ARG, "row range [%lld, %lld) outside [0, %d)", (long long)p->row_begin, re, p->M);
+    return LF_OK;
+}
+
+int check_volume(const lf_volume* v) {
+    if (!v) return fail(LF_E_ARG, "volume is NULL");
+    if (!v->data) return fail(LF_E_ARG, "volume data is NULL");
+    if (v->type < LF_VOX_U8 || v->type > LF_VOX_F32) return fail(LF_E_ARG, "unknown voxel type %d", v->type);
+    if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(LF_E_ARG, "volume dimensions must be >= 2");
+    if ((unsigned long long)v->nx * v->ny * v->nz >= (1ull << 32)) return fail(LF_E_RANGE, "volume too large");
+    if (v->brick != 0 && v->brick != 8) return fail(LF_E_UNSUPPORTED, "brick must be 0 or 8");
+    if (v->brick == 8 && (v->nx % 8 || v->ny % 8 || v->nz % 8))
+        return fail(LF_E_ARG, "bricked volume dimensions must be multiples of 8");
+    if (!(v->vmax > v->vmin) || !std::isfinite(v->vmin) || !std::isfinite(v->vmax))
+        return fail(LF_E_ARG, "vmax must exceed vmin");
+    for (int a = 0; a < 3; ++a)
+        if (!(v->box_max[a] > v->box_min[a]) || !std::isfinite(v->box_min[a]) || !std::isfinite(v->box_max[a]))
+            return fail(LF_E_ARG, "box_max must exceed box_min on every axis");
+    return LF_OK;
+}
+
+int check_medium(const lf_medium* m, const char* name) {
+    if (!m) return fail(LF_E_ARG, "%s medium is NULL", name);
+    if (!m->lut) return fail(LF_E_ARG, "%s lut is NULL", name);
+    if (m->lut_size < 2 || m->lut_size > 1024) return fail(LF_E_ARG, "%s lut_size must be in [2, 1024]", name);
+    if (!(m->density_scale >= 0.0f) || !std::isfinite(m->density_scale))
+        return fail(LF_E_ARG, "%s density_scale must be finite and >= 0", name);
+    return LF_OK;
+}
+
+int check_light(const lf_light* l) {
+    if (!l) return fail(LF_E_ARG, "light is NULL");
+    if (!finite3(l->radiance) || !finite3(l->env)) return fail(LF_E_ARG, "light radiance/env must be finite");
+    if (l->kind == LF_LIGHT_DIRECTIONAL) {
+        const double n = std::sqrt((double)l->dir[0] * l->dir[0] + (double)l->dir[1] * l->dir[1] +
+                                   (double)l->dir[2] * l->dir[2]);
+        if (!(std::fabs(n - 1.0) < 1e-3)) return fail(LF_E_ARG, "directional light dir must be a unit vector");
+    } else if (l->kind == LF_LIGHT_AREA) {
+        const double cx = (double)l->e1[1] * l->e2[2] - (double)l->e1[2] * l->e2[1];
+        const double cy = (double)l->e1[2] * l->e2[0] - (double)l->e1[0] * l->e2[2];
+        const double cz = (double)l->e1[0] * l->e2[1] - (double)l->e1[1] * l->e2[0];
+        if (!(cx * cx + cy * cy + cz * cz > 0.0) || !finite3(l->corner))
+            return fail(LF_E_ARG, "area light edges must span a parallelogram");
+    } else {
+        return fail(LF_E_ARG, "unknown light kind %d", l->kind);
+    }
+    return LF_OK;
+}
+
+void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, const lf_medium* s,
+                const lf_light* l, const lf_gen_params* p) {
+    std::memset(&T, 0, sizeof(T));
+    T.vol = v->data;
+    T.nx = v->nx;
+    T.ny = v->ny;
+    T.brick_row = 512 * (v->nx / 8);
+    T.brick_slab = 512 * (v->nx / 8) * (v->ny / 8);
+    const int n[3] = {v->nx, v->ny, v->nz};
+    for (int a = 0; a < 3; ++a) {
+        const double ext = (double)v->box_max[a] - (double)v->box_min[a];
+        T.ga[a] = (float)(n[a] / ext);
+        T.gb[a] = (float)(-(double)v->box_min[a] * n[a] / ext - 0.5);
+        T.gmax[a] = (float)(n[a] - 1);
+        T.imax[a] = n[a] - 2;
+        T.bmin[a] = v->box_min[a];
+        T.bmax[a] = v->box_max[a];
+    }
+    T.vmin = v->vmin;
+    T.vscale = (float)(1.0 / ((double)v->vmax - (double)v->vmin));
+    T.lut_n = e->lut_size;
+    T.lut_last = (float)(e->lut_size - 1);
+    T.lut_e = e->lut;
+    T.lut_s = s ? s->lut : e->lut;
+    T.scale_e = e->density_scale;
+    T.scale_s = s ? s->density_scale : e->density_scale;
+    T.light_kind = l->kind;
+    T.light_on = l->radiance[0] != 0.0f || l->radiance[1] != 0.0f || l->radiance[2] != 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        T.ldir[a] = l->dir[a];
+        T.lcorner[a] = l->corner[a];
+        T.le1[a] = l->e1[a];
+        T.le2[a] = l->e2[a];
+        T.lrad[a] = l->radiance[a];
+        T.env[a] = l->env[a];
+        T.O[a] = p->center[a];
+    }
+    if (l->kind == LF_LIGHT_DIRECTIONAL) {
+        const double nn = std::sqrt((double)l->dir[0] * l->dir[0] + (double)l->dir[1] * l->dir[1] +
+                                    (double)l->dir[2] * l->dir[2]);
+        for (int a = 0; a < 3; ++a) T.ldir[a] = (float)(l->dir[a] / nn);
+    } else {
+        const double c[3] = {(double)l->e1[1] * l->e2[2] - (double)l->e1[2] * l->e2[1],
+                             (double)l->e1[2] * l->e2[0] - (double)l->e1[0] * l->e2[2],
+                             (double)l->e1[0] * l->e2[1] - (double)l->e1[1] * l->e2[0]};
+        const double area = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        for (int a = 0; a < 3; ++a) T.lnrm[a] = (float)(c[a] / area);
+        T.larea = (float)area;
+    }
+    T.M = p->M;
+    T.N = p->N;
+    T.R = p->radius;
+    T.spp = p->spp;
+    T.maxb = p->max_bounces;
+    T.g = p->hg_g;
+    T.key0 = (uint32_t)p->seed;
+    T.key1 = (uint32_t)(p->seed >> 32);
+    T.jitter = p->jitter != 0;
+    T.jit_rad = (float)(2.0 * p->radius / std::sqrt((double)p->M));
+    T.row_begin = (int32_t)p->row_begin;
+    T.row_end = (int32_t)(p->row_end <= 0 ? p->M : p->row_end);
+    T.stats = (unsigned long long*)p->stats;
+}
+
+int check_workspace(void* ws, size_t* ws_bytes) {
+    if (!ws_bytes) return fail(LF_E_ARG, "ws_bytes is NULL");
+    if (!ws) return 1;  // size query
+    if (*ws_bytes < kWorkspaceBytes)
+        return fail(LF_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", *ws_bytes,
+                    kWorkspaceBytes);
+    if ((uintptr_t)ws % 16) return fail(LF_E_WORKSPACE, "workspace must be 16-byte aligned");
+    return LF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lf_last_error(void) { return g_err.c_str(); }
+
+int lf_version(void) { return LUMIPATH_VERSION; }
+
+int lf_points(int32_t n, float* xyz_out, const float* query, int64_t nq, int32_t K, int32_t* idx_out,
+              float* w_out, void* stream) {
+    g_err.clear();
+    if (n < 1 || n > 65535) return fail(LF_E_ARG, "n must be in [1, 65535] (got %d)", n);
+    if (!xyz_out && !query) return fail(LF_E_ARG, "nothing to do: xyz_out and query are NULL");
+    if (query) {
+        if (nq < 0) return fail(LF_E_ARG, "nq must be >= 0");
+        if (K < 1 || K > 9) return fail(LF_E_ARG, "K must be in [1, 9] (got %d)", K);
+        if (!idx_out) return fail(LF_E_ARG, "idx_out is NULL");
+        if (nq > (1ll << 40)) return fail(LF_E_RANGE, "too many queries");
+    }
+    hipError_t e = lp::launch_points(n, xyz_out, query, query ? nq : 0, K, idx_out, w_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lf_points");
+    return LF_OK;
+}
+
+int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sample, const lf_light* light,
+                const lf_gen_params* params, int32_t dtype, void* lf_out, void* ws, size_t* ws_bytes,
+                void* stream) {
+    g_err.clear();
+    int r;
+    if ((r = check_volume(vol)) || (r = check_medium(eval, "eval")) || (r = check_light(light)) ||
+        (r = check_params(params, true)))
+        return r;
+    if (sample) {
+        if ((r = check_medium(sample, "sample"))) return r;
+        if (sample->lut_size != eval->lut_size) return fail(LF_E_ARG, "sample and eval LUT sizes differ");
+    }
+    if (dtype < LF_F32 || dtype > LF_BF16) return fail(LF_E_ARG, "unknown light-field dtype %d", dtype);
+    if (!lf_out) return fail(LF_E_ARG, "lf_out is NULL");
+    r = check_workspace(ws, ws_bytes);
+    if (r == 1) {
+        *ws_bytes = kWorkspaceBytes;
+        return LF_OK;
+    }
+    if (r) return r;
+    lp::TraceParams T;
+    pack_trace(T, vol, eval, sample, light, params);
+    T.out = lf_out;
+    T.dtype = dtype;
+    float* sig = (float*)ws;
+    T.sigbar = sig;
+    const lf_medium* sm = sample ? sample : eval;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = lp::launch_majorant(sm->lut, sm->lut_size, sm->density_scale, params->majorant, sig, s);
+    if (e != hipSuccess) return hip_fail(e, "lf_generate (majorant)");
+    const int mode = (sample && sample != eval) ? lp::kFrozen : lp::kFwd;
+    e = lp::launch_generate(T, vol->type, vol->brick == 8, mode, s);
+    if (e != hipSuccess) return hip_fail(e, "lf_generate");
+    return LF_OK;
+}
+
+int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf_light* light,
+                         const lf_gen_params* params, const float* d_lf, float* d_lut, float* d_scale, void* ws,
+                         size_t* ws_bytes, void* stream) {
+    g_err.clear();
+    int r;
+    if ((r = check_volume(vol)) || (r = check_medium(medium, "")) || (r = check_light(light)) ||
+        (r = check_params(params, true)))
+        return r;
+    if (!d_lf || !d_lut || !d_scale) return fail(LF_E_ARG, "d_lf, d_lut and d_scale must be non-NULL");
+    r = check_workspace(ws, ws_bytes);
+    if (r == 1) {
+        *ws_bytes = kWorkspaceBytes;
+        return LF_OK;
+    }
+    if (r) return r;
+    lp::TraceParams T;
+    pack_trace(T, vol, medium, nullptr, light, params);
+    T.d_lf = d_lf;
+    T.d_lut = d_lut;
+    T.d_scale = d_scale;
+    T.stats = nullptr;
+    float* sig = (float*)ws;
+    T.sigbar = sig;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = lp::launch_zero(d_lut, 4ll * medium->lut_size, s);
+    if (e == hipSuccess) e = lp::launch_zero(d_scale, 1, s);
+    if (e == hipSuccess)
+        e = lp::launch_majorant(medium->lut, medium->lut_size, medium->density_scale, params->majorant, sig, s);
+    if (e == hipSuccess) e = lp::launch_generate(T, vol->type, vol->brick == 8, lp::kGrad, s);
+    if (e != hipSuccess) return hip_fail(e, "lf_generate_backward");
+    return LF_OK;
+}
+
+int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
+              int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out,
+              void* stream) {
+    g_err.clear();
+    int r;
+    if ((r = check_params(params, false))) return r;
+    if (!cams) return fail(LF_E_ARG, "cams is NULL");
+    if (n_views < 1 || W < 1 || H < 1) return fail(LF_E_ARG, "n_views, W and H must be >= 1");
+    if ((long long)W * H > (1ll << 30) || (long long)n_views * W * H > (1ll << 40))
+        return fail(LF_E_RANGE, "image too large");
+    if (K < 1 || K > 9) return fail(LF_E_ARG, "K must be in [1, 9] (got %d)", K);
+    if (mode != LF_LOOKUP_FORWARD && mode != LF_LOOKUP_ADJOINT) return fail(LF_E_ARG, "unknown mode %d", mode);
+    if (dtype < LF_F32 || dtype > LF_BF16) return fail(LF_E_ARG, "unknown light-field dtype %d", dtype);
+    if (!img) return fail(LF_E_ARG, "img is NULL");
+    if (mode == LF_LOOKUP_FORWARD && !lf) return fail(LF_E_ARG, "lf is NULL");
+    if (mode == LF_LOOKUP_ADJOINT && !d_lf) return fail(LF_E_ARG, "d_lf is NULL");
+    const double R = params->radius;
+    lp::LookupParams L;
+    std::memset(&L, 0, sizeof(L));
+    L.M = params->M;
+    L.N = params->N;
+    L.invM = (float)(1.0 / params->M);
+    L.invN = (float)(1.0 / params->N);
+    L.inv_rM = (float)(1.0 / std::sqrt(4.0 * M_PI / params->M));
+    L.inv_rN = (float)(1.0 / std::sqrt(4.0 * M_PI / params->N));
+    L.W = W;
+    L.H = H;
+    L.K = K;
+    L.dtype = dtype;
+    L.degenerate = params->M == params->N;
+    L.thr = (float)(1e-6 * R * R);
+    L.lf = lf;
+    L.img = img;
+    L.d_lf = d_lf;
+    L.nn = nn_out;
+    // per-view geometry in double, rounded once to float
+    std::vector<lp::ViewGeom> geo((size_t)n_views);
+    for (int v = 0; v < n_views; ++v) {
+        const lf_camera& c = cams[v];
+        double oc[3], f[3], u[3], rt[3], up[3];
+        for (int a = 0; a < 3; ++a) {
+            oc[a] = (double)c.eye[a] - params->center[a];
+            f[a] = (double)c.target[a] - c.eye[a];
+            u[a] = c.up[a];
+        }
+        const double occ = oc[0] * oc[0] + oc[1] * oc[1] + oc[2] * oc[2];
+        const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        if (!(occ > R * R)) {
+            return fail(LF_E_ARG, "camera %d: eye is inside the bounding sphere", v);
+        }
+        if (!(c.vfov > 0.0f && c.vfov < 3.14159f) || !(fl > 0.0)) {
+            return fail(LF_E_ARG, "camera %d: bad field of view or target", v);
+        }
+        for (int a = 0; a < 3; ++a) f[a] /= fl;
+        rt[0] = f[1] * u[2] - f[2] * u[1];
+        rt[1] = f[2] * u[0] - f[0] * u[2];
+        rt[2] = f[0] * u[1] - f[1] * u[0];
+        const double rl = std::sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+        if (!(rl > 1e-9)) {
+            return fail(LF_E_ARG, "camera %d: up is parallel to the view direction", v);
+        }
+        for (int a = 0; a < 3; ++a) rt[a] /= rl;
+        up[0] = rt[1] * f[2] - rt[2] * f[1];
+        up[1] = rt[2] * f[0] - rt[0] * f[2];
+        up[2] = rt[0] * f[1] - rt[1] * f[0];
+        const double th = std::tan(0.5 * c.vfov);
+        lp::ViewGeom& g = geo[v];
+        for (int a = 0; a < 3; ++a) {
+            g.oc[a] = (float)oc[a];
+            g.fwd[a] = (float)f[a];
+            g.right[a] = (float)rt[a];
+            g.up[a] = (float)up[a];
+        }
+        g.c = (float)(occ - R * R);
+        g.sx = (float)(th * (double)W / (double)H);
+        g.sy = (float)th;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int v0 = 0; v0 < n_views; v0 += lp::kMaxViewsPerLaunch) {
+        const int nv = std::min(lp::kMaxViewsPerLaunch, n_views - v0);
+        L.view0 = v0;
+        L.nviews = nv;
+        for (int v = 0; v < nv; ++v) L.v[v] = geo[v0 + v];
+        hipError_t e = lp::launch_lookup(L, mode, s);
+        if (e != hipSuccess) return hip_fail(e, "lf_lookup");
+    }
+    return LF_OK;
+}
+
+}  // extern "C"

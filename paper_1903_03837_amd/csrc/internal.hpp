@@ -1,0 +1,42 @@
+// internal.hpp -- launch entry points of the kernels, called by the C ABI in
+// api.cpp after argument validation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tracer_device.hpp"
+
+namespace lp {
+
+constexpr int kMaxViewsPerLaunch = 24;
+
+struct ViewGeom {
+    float oc[3];      // eye - O
+    float fwd[3], right[3], up[3];
+    float c;          // |eye - O|^2 - R^2
+    float sx, sy;     // tan(vfov / 2) * aspect, tan(vfov / 2)
+};
+
+struct LookupParams {
+    int32_t M, N;
+    float invM, invN;
+    float inv_rM, inv_rN;   // 1 / sqrt(4 pi / n)
+    int32_t W, H, K;
+    int32_t nviews, view0;
+    int32_t dtype, degenerate;
+    float thr;              // tangent threshold 1e-6 R^2
+    const void* lf;
+    float* img;
+    float* d_lf;
+    int32_t* nn;
+    ViewGeom v[kMaxViewsPerLaunch];
+};
+
+hipError_t launch_points(int n, float* xyz, const float* query, long long nq, int K, int* idx, float* w,
+                         hipStream_t s);
+hipError_t launch_majorant(const float* lut, int lut_n, float scale, float given, float* out, hipStream_t s);
+hipError_t launch_generate(const TraceParams& P, int vtype, int brick, int mode, hipStream_t s);
+hipError_t launch_zero(float* p, long long n, hipStream_t s);
+hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s);
+
+}  // namespace lp

@@ -1,0 +1,226 @@
+// lookup.hip -- image synthesis from the light field (Sec. 2, Fig. 2) and
+// its transpose.
+//
+// One lane per pixel; a wave64 covers an 8 x 8 pixel tile and a workgroup a
+// 16 x 16 tile, so neighbouring lanes query neighbouring points of both SF
+// sets and their K x K texel gathers hit the same cache lines.  Per pixel:
+// view ray -> front/back hits on S (tangential rays discarded) -> O(1)
+// inverse SF mapping of each hit -> K nearest of the nine lattice
+// candidates -> tent weights -> K x K gathers (25 at K = 5) -> normalised
+// blend.  The adjoint mode scatters weight x d(img) into d(Lhat) with float
+// atomics.
+#include <hip/hip_fp16.h>
+
+#include "internal.hpp"
+
+namespace lp {
+
+template <int DT>
+__device__ __forceinline__ f3 load_texel(const void* lf, uint64_t t) {
+    if constexpr (DT == 0) {
+        const float* p = (const float*)lf + 3 * t;
+        return mk3(p[0], p[1], p[2]);
+    } else if constexpr (DT == 1) {
+        const __half* p = (const __half*)lf + 3 * t;
+        return mk3(__half2float(p[0]), __half2float(p[1]), __half2float(p[2]));
+    } else {
+        const uint16_t* p = (const uint16_t*)lf + 3 * t;
+        return mk3(__uint_as_float((uint32_t)p[0] << 16), __uint_as_float((uint32_t)p[1] << 16),
+                   __uint_as_float((uint32_t)p[2] << 16));
+    }
+}
+
+template <int KMAX, int DT, int MODE>
+__global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int v = blockIdx.z;
+    if (px >= P.W || py >= P.H) return;
+    const ViewGeom& G = P.v[v];
+    const uint64_t pix = ((uint64_t)(P.view0 + v) * P.H + py) * P.W + px;
+    const float ndx = (2.0f * ((float)px + 0.5f) / (float)P.W - 1.0f) * G.sx;
+    const float ndy = (1.0f - 2.0f * ((float)py + 0.5f) / (float)P.H) * G.sy;
+    const f3 fwd = mk3(G.fwd[0], G.fwd[1], G.fwd[2]);
+    const f3 rt = mk3(G.right[0], G.right[1], G.right[2]);
+    const f3 up = mk3(G.up[0], G.up[1], G.up[2]);
+    const f3 d = normalize(fwd + rt * ndx + up * ndy);
+    const f3 oc = mk3(G.oc[0], G.oc[1], G.oc[2]);
+    const float b = dot(d, oc);
+    const float disc = b * b - G.c;
+    if (!(disc > P.thr)) {
+        if constexpr (MODE == 0) {
+            float* o = P.img + 3 * pix;
+            o[0] = o[1] = o[2] = 0.0f;
+        }
+        if (P.nn) {
+            P.nn[2 * pix] = -1;
+            P.nn[2 * pix + 1] = -1;
+        }
+        return;
+    }
+    const float sq = sqrtf(disc);
+    const f3 qo = normalize(fma3(d, -b - sq, oc));
+    const f3 qd = normalize(fma3(d, -b + sq, oc));
+
+    int ia[KMAX], jb[KMAX];
+    float da[KMAX], db[KMAX];
+    {
+        Cand9 C;
+        const int k = sf_zone(P.M, qo.z);
+        sf_nearest(P.M, P.invM, qo, k, C);
+        select_k<KMAX>(C, P.K, ia, da);
+    }
+    {
+        Cand9 C;
+        const int k = sf_zone(P.N, qd.z);
+        sf_nearest(P.N, P.invN, qd, k, C);
+        select_k<KMAX>(C, P.K, jb, db);
+    }
+    if (P.nn) {
+        P.nn[2 * pix] = ia[0];
+        P.nn[2 * pix + 1] = jb[0];
+    }
+
+    if constexpr (KMAX == 1) {
+        const uint64_t t = (uint64_t)ia[0] * (uint64_t)P.N + (uint64_t)jb[0];
+        if constexpr (MODE == 0) {
+            const f3 c = load_texel<DT>(P.lf, t);
+            float* o = P.img + 3 * pix;
+            o[0] = c.x;
+            o[1] = c.y;
+            o[2] = c.z;
+        } else {
+            const float* g = P.img + 3 * pix;
+            float* dl = P.d_lf + 3 * t;
+            atomicAdd(dl + 0, g[0]);
+            atomicAdd(dl + 1, g[1]);
+            atomicAdd(dl + 2, g[2]);
+        }
+        return;
+    }
+
+    float wa[KMAX], wb[KMAX];
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+        wa[a] = ia[a] >= 0 ? tent_weight(da[a], P.inv_rM) : 0.0f;
+        wb[a] = jb[a] >= 0 ? tent_weight(db[a], P.inv_rN) : 0.0f;
+    }
+    float wsum = 0.0f;
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) {
+            const bool bad = P.degenerate && ia[a] == jb[c];
+            wsum += bad ? 0.0f : wa[a] * wb[c];
+        }
+    if constexpr (MODE == 0) {
+        f3 acc = mk3(0.0f, 0.0f, 0.0f);
+        if (wsum > 0.0f) {
+            const float inv = 1.0f / wsum;
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) {
+                    const bool bad = P.degenerate && ia[a] == jb[c];
+                    const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
+                    // unconditional, in-range gathers so all KMAX^2 loads issue together
+                    const uint64_t t = (uint64_t)max(ia[a], 0) * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
+                    acc = fma3(load_texel<DT>(P.lf, t), w, acc);
+                }
+        }
+        float* o = P.img + 3 * pix;
+        o[0] = acc.x;
+        o[1] = acc.y;
+        o[2] = acc.z;
+    } else {
+        if (!(wsum > 0.0f)) return;
+        const float inv = 1.0f / wsum;
+        const float* g = P.img + 3 * pix;
+        const f3 gi = mk3(g[0], g[1], g[2]);
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+                const bool bad = P.degenerate && ia[a] == jb[c];
+                const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
+                if (w != 0.0f) {
+                    float* dl = P.d_lf + 3 * ((uint64_t)ia[a] * (uint64_t)P.N + (uint64_t)jb[c]);
+                    atomicAdd(dl + 0, w * gi.x);
+                    atomicAdd(dl + 1, w * gi.y);
+                    atomicAdd(dl + 2, w * gi.z);
+                }
+            }
+    }
+}
+
+template <int KMAX, int DT>
+static hipError_t launch_lookup_mode(const LookupParams& P, int mode, hipStream_t s) {
+    dim3 grid((P.W + 15) / 16, (P.H + 15) / 16, P.nviews);
+    if (mode == 0) lookup_kernel<KMAX, DT, 0><<<grid, 256, 0, s>>>(P);
+    else lookup_kernel<KMAX, DT, 1><<<grid, 256, 0, s>>>(P);
+    return hipGetLastError();
+}
+
+template <int KMAX>
+static hipError_t launch_lookup_dt(const LookupParams& P, int mode, hipStream_t s) {
+    switch (P.dtype) {
+        case 0: return launch_lookup_mode<KMAX, 0>(P, mode, s);
+        case 1: return launch_lookup_mode<KMAX, 1>(P, mode, s);
+        default: return launch_lookup_mode<KMAX, 2>(P, mode, s);
+    }
+}
+
+hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s) {
+    if (P.K == 1) return launch_lookup_dt<1>(P, mode, s);
+    if (P.K <= 5) return launch_lookup_dt<5>(P, mode, s);
+    return launch_lookup_dt<9>(P, mode, s);
+}
+
+// ---------------------------------------------------------------------------
+// lf_points: the point set and the inverse query
+// ---------------------------------------------------------------------------
+__global__ void points_kernel(int n, float inv_n, float* xyz) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const f3 p = sf_point(n, i, inv_n);
+    xyz[3 * i] = p.x;
+    xyz[3 * i + 1] = p.y;
+    xyz[3 * i + 2] = p.z;
+}
+
+template <int KMAX>
+__global__ void query_kernel(int n, float inv_n, float inv_r, const float* query, long long nq, int K, int* idx,
+                             float* w) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const f3 v = normalize(mk3(query[3 * q], query[3 * q + 1], query[3 * q + 2]));
+    Cand9 C;
+    const int k = sf_zone(n, v.z);
+    sf_nearest(n, inv_n, v, k, C);
+    int id[KMAX];
+    float d2[KMAX];
+    select_k<KMAX>(C, K, id, d2);
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+        if (a >= K) break;
+        idx[q * K + a] = id[a];
+        if (w) w[q * K + a] = id[a] >= 0 ? tent_weight(d2[a], inv_r) : 0.0f;
+    }
+}
+
+hipError_t launch_points(int n, float* xyz, const float* query, long long nq, int K, int* idx, float* w,
+                         hipStream_t s) {
+    const float inv_n = 1.0f / (float)n;
+    if (xyz) points_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, inv_n, xyz);
+    if (query && nq > 0) {
+        const float inv_r = 1.0f / sqrtf(4.0f * kPi * inv_n);
+        const unsigned blocks = (unsigned)((nq + 255) / 256);
+        if (K == 1) query_kernel<1><<<blocks, 256, 0, s>>>(n, inv_n, inv_r, query, nq, K, idx, w);
+        else if (K <= 5) query_kernel<5><<<blocks, 256, 0, s>>>(n, inv_n, inv_r, query, nq, K, idx, w);
+        else query_kernel<9><<<blocks, 256, 0, s>>>(n, inv_n, inv_r, query, nq, K, idx, w);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lp

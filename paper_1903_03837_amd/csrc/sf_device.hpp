@@ -1,0 +1,231 @@
+// sf_device.hpp -- device building blocks shared by the light-field kernels:
+// small vector algebra, Philox4x32-10, the spherical-Fibonacci point set and
+// its O(1) inverse (nearest point and "up to nine" neighbours).
+//
+// Spherical Fibonacci set (Fink et al. 2019, Sec. 2, SF point equation):
+//   p_i = (cos phi_i sin theta_i, sin phi_i sin theta_i, z_i),
+//   phi_i = 2 pi frac(i (Phi - 1)), z_i = 1 - (2i + 1) / n.
+// frac(i (Phi - 1)) is the one step computed in FP64: in FP32 its error grows
+// with i and reaches half the point spacing near n = 32768.
+//
+// Inverse mapping (Keinert et al. 2015, used in Sec. 2): in the (phi, z)
+// plane the points form a lattice spanned by the index steps F(k), F(k+1)
+// (consecutive Fibonacci numbers) of the zone k around the query height.
+// Solving for the lattice cell that holds the query and testing its four
+// corners gives the nearest point; a short descent over the eight lattice
+// neighbours then absorbs FP32 slips at cell boundaries.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lp {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr double kPiD = 3.14159265358979323846;
+constexpr double kPhiM1 = 0.61803398874989484820;       // Phi - 1 = 1 / Phi
+constexpr float kInvLogPhi2 = 1.0390834931f;             // 1 / ln(Phi^2)
+constexpr float kPiSqrt5 = 7.0248147310f;                // pi * sqrt(5)
+
+struct f3 {
+    float x, y, z;
+};
+__device__ __forceinline__ f3 mk3(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ f3 operator*(f3 a, f3 b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 normalize(f3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+__device__ __forceinline__ f3 fma3(f3 a, float s, f3 b) {  // a * s + b
+    return {fmaf(a.x, s, b.x), fmaf(a.y, s, b.y), fmaf(a.z, s, b.z)};
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The 32x32->64 products
+// map to v_mad_u64_u32.
+// ---------------------------------------------------------------------------
+struct u4 {
+    uint32_t x, y, z, w;
+};
+__device__ __forceinline__ u4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * c0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi_a = (uint32_t)(a >> 32), lo_a = (uint32_t)a;
+        const uint32_t hi_b = (uint32_t)(b >> 32), lo_b = (uint32_t)b;
+        c0 = hi_b ^ c1 ^ k0;
+        c2 = hi_a ^ c3 ^ k1;
+        c1 = lo_b;
+        c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+// 24-bit uniform in [0, 1), exact in binary32.
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-08f; }
+
+// ---------------------------------------------------------------------------
+// Spherical-Fibonacci points
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sf_frac(int i) {
+    double f = (double)i * kPhiM1;
+    return (float)(f - floor(f));
+}
+__device__ __forceinline__ f3 sf_point(int n, int i, float inv_n) {
+    float s, c;
+    sincospif(2.0f * sf_frac(i), &s, &c);
+    const uint32_t a = 2u * (uint32_t)i + 1u;
+    const uint32_t b = 2u * (uint32_t)n - a;
+    const float st = sqrtf((float)((uint64_t)a * b)) * inv_n;
+    const float z = (float)(n - 2 * i - 1) * inv_n;
+    return {c * st, s * st, z};
+}
+
+__device__ __forceinline__ int fib(int k) {
+    // F(0..24); k stays below 20 for n <= 65535
+    constexpr int t[25] = {0,   1,   1,   2,    3,    5,    8,    13,   21,   34,    55,    89,   144,
+                           233, 377, 610, 987, 1597, 2584, 4181, 6765, 10946, 17711, 28657, 46368};
+    return t[k];
+}
+
+// Zone number k = max(2, floor(log_{Phi^2}(n pi sqrt5 (1 - z^2)))).
+__device__ __forceinline__ int sf_zone(int n, float qz) {
+    const float arg = (float)n * kPiSqrt5 * ((1.0f - qz) * (1.0f + qz));
+    if (!(arg > 0.0f)) return 2;
+    const int k = (int)floorf(logf(arg) * kInvLogPhi2);
+    return k < 2 ? 2 : (k > 20 ? 20 : k);
+}
+
+// Signed azimuth step of the index step F: 2 pi (F (Phi-1) - round(F (Phi-1))).
+__device__ __forceinline__ float sf_dphi(int F) {
+    double x = (double)F * kPhiM1;
+    return (float)(2.0 * kPiD * (x - rint(x)));
+}
+
+__device__ __forceinline__ float dist2(f3 q, f3 p) {
+    const f3 d = q - p;
+    return dot(d, d);
+}
+__device__ __forceinline__ bool closer(float da, int ia, float db, int ib) {
+    return da < db || (da == db && ia < ib);
+}
+
+// Nearest point by the lattice-cell corners (no descent yet).
+__device__ __forceinline__ int sf_cell_nearest(int n, float inv_n, f3 q, int k, float& best_d2) {
+    const int F0 = fib(k), F1 = fib(k + 1);
+    const float b00 = sf_dphi(F0), b01 = sf_dphi(F1);
+    const float b10 = -2.0f * (float)F0 * inv_n, b11 = -2.0f * (float)F1 * inv_n;
+    const float inv_det = 1.0f / (b00 * b11 - b01 * b10);
+    const float z0 = 1.0f - inv_n;
+    const float v0 = atan2f(q.y, q.x), v1 = q.z - z0;
+    const float c0 = floorf((b11 * v0 - b01 * v1) * inv_det);
+    const float c1 = floorf((b00 * v1 - b10 * v0) * inv_det);
+    int best = -1;
+    float bd = 3.402823466e38f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float zc = b10 * (c0 + (float)(s & 1)) + b11 * (c1 + (float)(s >> 1)) + z0;
+        zc = fminf(fmaxf(zc, -1.0f), 1.0f) * 2.0f - zc;  // mirror heights past a pole
+        int i = (int)floorf(0.5f * (float)n * (1.0f - zc));
+        i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+        const float d = dist2(q, sf_point(n, i, inv_n));
+        if (closer(d, i, bd, best)) {
+            bd = d;
+            best = i;
+        }
+    }
+    best_d2 = bd;
+    return best;
+}
+
+// Candidate set of a centre index: c + {0, +-F(k-1), +-F(k), +-F(k+1),
+// +-F(k+2)} inside [0, n), duplicates (zone 2: F(1) = F(2)) replaced by
+// invalid entries (d2 = +inf, distinct large keys).
+struct Cand9 {
+    int idx[9];
+    float d2[9];
+};
+__device__ __forceinline__ void sf_candidates(int n, float inv_n, f3 q, int k, int c, Cand9& C) {
+    const int f1 = fib(k - 1), f2 = fib(k), f3v = fib(k + 1), f4 = fib(k + 2);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        int off = 0;
+        if (t > 0) {
+            const int m = (t - 1) >> 1;
+            const int f = m == 0 ? f1 : (m == 1 ? f2 : (m == 2 ? f3v : f4));
+            off = (t & 1) ? f : -f;
+        }
+        const int ci = c + off;
+        const bool dup = (t == 1 || t == 2) && f1 == f2;
+        const bool ok = ci >= 0 && ci < n && !dup;
+        C.idx[t] = ok ? ci : 0x7fffff00 + t;
+        C.d2[t] = ok ? dist2(q, sf_point(n, ci, inv_n)) : 3.402823466e38f;
+    }
+}
+
+// Nearest point: lattice corners, then descent over the candidate set until
+// the centre is the closest candidate.  Leaves that final set in C.
+__device__ __forceinline__ int sf_nearest(int n, float inv_n, f3 q, int k, Cand9& C) {
+    float bd;
+    int c = sf_cell_nearest(n, inv_n, q, k, bd);
+    for (int it = 0; it < 16; ++it) {
+        sf_candidates(n, inv_n, q, k, c, C);
+        int best = C.idx[0];
+        float bdd = C.d2[0];
+#pragma unroll
+        for (int t = 1; t < 9; ++t)
+            if (closer(C.d2[t], C.idx[t], bdd, best)) {
+                bdd = C.d2[t];
+                best = C.idx[t];
+            }
+        if (best == c) break;
+        c = best;
+    }
+    return c;
+}
+
+// Keep the K nearest candidates in (distance^2, index) order.  Fully
+// unrolled rank selection so every array stays in registers.
+template <int KMAX>
+__device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, float* out_d2) {
+    int rank[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        int r = 0;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) r += (b != a) && closer(C.d2[b], C.idx[b], C.d2[a], C.idx[a]);
+        rank[a] = r;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < KMAX; ++r) {
+        int id = -1;
+        float d = 3.402823466e38f;
+#pragma unroll
+        for (int a = 0; a < 9; ++a)
+            if (rank[a] == r) {
+                id = C.idx[a];
+                d = C.d2[a];
+            }
+        const bool ok = r < K && id >= 0 && id < 0x7fffff00;
+        out_idx[r] = ok ? id : -1;
+        out_d2[r] = d;
+        cnt += ok;
+    }
+    return cnt;
+}
+
+// Tent filter of radius sqrt(4 pi / n) on the unit chord (Sec. 2 filter
+// kernel of size R sqrt(4 pi / N), with R scaled out).
+__device__ __forceinline__ float tent_weight(float d2, float inv_r) {
+    return fmaxf(0.0f, 1.0f - sqrtf(d2) * inv_r);
+}
+
+}  // namespace lp

@@ -1,0 +1,426 @@
+// tracer_device.hpp -- the volumetric path tracer behind lf_generate and
+// lf_generate_backward.
+//
+// Each GPU lane owns one ray r_k of the SF ray set (Sec. 2, ray equation),
+// and traces all of its samples in order, so the FP32 sum per texel is
+// deterministic.  Transport (the volumetric reading of Sec. 2's "conventional
+// path tracer"):
+//   - origin jitter on the disk of area 4 pi R^2 / M in the tangent plane;
+//   - delta tracking against a global majorant sigma_bar;
+//   - real collision: throughput times the albedo, next-event estimation
+//     towards the light with ratio-tracking transmittance, Henyey-Greenstein
+//     direction for the next segment; escape: constant environment.
+// Random numbers: Philox4x32-10 keyed by the seed, counter (ray, sample,
+// bounce << 8 | purpose, block); one block feeds two tentative collisions or
+// four shadow steps.
+//
+// The same routine runs in three modes:
+//   kFwd     plain estimator;
+//   kFrozen  decisions with the sampling medium, importance weights to the
+//            evaluated medium (finite-difference hook of the adjoint);
+//   kGrad    replay of a sample whose total radiance is known: every event
+//            scatters its score times the radiance gathered after it into
+//            LDS accumulators (dLUT, dscale).
+#pragma once
+
+#include "sf_device.hpp"
+
+namespace lp {
+
+enum { kFwd = 0, kFrozen = 1, kGrad = 2 };
+enum { kPurJitter = 0, kPurFlight = 1, kPurVertex = 2, kPurShadow = 3 };
+// At most 2^20 tentative collisions per segment (free flight or shadow ray).
+// Valid scenes stay orders of magnitude below; a segment that reaches it ends
+// absorbed (free flight) or fully blocked (shadow), so no lane can spin.
+constexpr uint32_t kMaxFlightBlocks = 1u << 19;  // 2 collisions per block
+constexpr uint32_t kMaxShadowBlocks = 1u << 18;  // 4 steps per block
+
+struct TraceParams {
+    // volume
+    const void* vol;
+    int32_t nx, ny;
+    int32_t brick_row, brick_slab;   // bricked: 512 * nbx, 512 * nbx * nby
+    float ga[3], gb[3];              // grid coordinate = x * ga + gb
+    float gmax[3];                   // n - 1
+    int32_t imax[3];                 // n - 2
+    float vmin, vscale;              // s = (v - vmin) * vscale
+    int32_t lut_n;
+    float lut_last;                  // lut_n - 1
+    const float* lut_e;              // [lut_n][4]
+    const float* lut_s;
+    float scale_e, scale_s;
+    float bmin[3], bmax[3];
+    // light
+    int32_t light_kind, light_on;
+    float ldir[3], lcorner[3], le1[3], le2[3], lrad[3], lnrm[3];
+    float larea;
+    float env[3];
+    // ray set
+    int32_t M, N;
+    float O[3], R;
+    int32_t spp, maxb;
+    float g;
+    uint32_t key0, key1;
+    int32_t jitter;
+    float jit_rad;                   // 2 R / sqrt(M)
+    int32_t row_begin, row_end;
+    const float* sigbar;             // device scalar
+    // outputs
+    void* out;
+    int32_t dtype;
+    unsigned long long* stats;
+    // adjoint
+    const float* d_lf;
+    float* d_lut;
+    float* d_scale;
+};
+
+struct Counters {
+    uint32_t tent, shadow, real, samples;
+};
+
+// ---------------------------------------------------------------------------
+// Medium
+// ---------------------------------------------------------------------------
+template <int VT>
+__device__ __forceinline__ float vox(const void* v, uint32_t idx) {
+    if constexpr (VT == 0) return (float)((const uint8_t*)v)[idx];
+    else if constexpr (VT == 1) return (float)((const uint16_t*)v)[idx];
+    else return ((const float*)v)[idx];
+}
+
+template <int BR>
+__device__ __forceinline__ uint32_t ax_x(int x) { return BR ? (uint32_t)((x >> 3) * 512 + (x & 7)) : (uint32_t)x; }
+
+// Trilinear raw value at world point y (edge-clamped grid coordinates).
+template <int VT, int BR>
+__device__ __forceinline__ float sample_volume(const TraceParams& P, f3 y) {
+    const float gx = fminf(fmaxf(fmaf(y.x, P.ga[0], P.gb[0]), 0.0f), P.gmax[0]);
+    const float gy = fminf(fmaxf(fmaf(y.y, P.ga[1], P.gb[1]), 0.0f), P.gmax[1]);
+    const float gz = fminf(fmaxf(fmaf(y.z, P.ga[2], P.gb[2]), 0.0f), P.gmax[2]);
+    const int ix = min((int)gx, P.imax[0]);
+    const int iy = min((int)gy, P.imax[1]);
+    const int iz = min((int)gz, P.imax[2]);
+    const float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
+    uint32_t x0, x1, y0, y1, z0, z1;
+    if constexpr (BR) {
+        x0 = ax_x<1>(ix);
+        x1 = ax_x<1>(ix + 1);
+        y0 = (uint32_t)((iy >> 3) * P.brick_row + (iy & 7) * 8);
+        y1 = (uint32_t)(((iy + 1) >> 3) * P.brick_row + ((iy + 1) & 7) * 8);
+        z0 = (uint32_t)((iz >> 3) * P.brick_slab + (iz & 7) * 64);
+        z1 = (uint32_t)(((iz + 1) >> 3) * P.brick_slab + ((iz + 1) & 7) * 64);
+    } else {
+        x0 = (uint32_t)ix;
+        x1 = x0 + 1;
+        y0 = (uint32_t)iy * (uint32_t)P.nx;
+        y1 = y0 + (uint32_t)P.nx;
+        z0 = (uint32_t)iz * (uint32_t)P.nx * (uint32_t)P.ny;
+        z1 = z0 + (uint32_t)P.nx * (uint32_t)P.ny;
+    }
+    const float v000 = vox<VT>(P.vol, x0 + y0 + z0), v100 = vox<VT>(P.vol, x1 + y0 + z0);
+    const float v010 = vox<VT>(P.vol, x0 + y1 + z0), v110 = vox<VT>(P.vol, x1 + y1 + z0);
+    const float v001 = vox<VT>(P.vol, x0 + y0 + z1), v101 = vox<VT>(P.vol, x1 + y0 + z1);
+    const float v011 = vox<VT>(P.vol, x0 + y1 + z1), v111 = vox<VT>(P.vol, x1 + y1 + z1);
+    const float c00 = fmaf(fx, v100 - v000, v000), c10 = fmaf(fx, v110 - v010, v010);
+    const float c01 = fmaf(fx, v101 - v001, v001), c11 = fmaf(fx, v111 - v011, v011);
+    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, c1 - c0, c0);
+}
+
+struct TF {
+    int l0;
+    float w;
+    float a;        // alpha of the evaluated medium
+    float a_s;      // alpha of the sampling medium (kFrozen)
+    f3 rgb;         // evaluated colour, unclamped
+};
+
+// Post-classification: window, clamp, linear LUT interpolation (LUT in LDS).
+template <int MODE>
+__device__ __forceinline__ TF classify(const TraceParams& P, const float4* lut_e, const float4* lut_s, float raw) {
+    TF t;
+    const float s = fminf(fmaxf((raw - P.vmin) * P.vscale, 0.0f), 1.0f);
+    const float u = s * P.lut_last;
+    t.l0 = min((int)u, P.lut_n - 2);
+    t.w = u - (float)t.l0;
+    const float4 A = lut_e[t.l0], B = lut_e[t.l0 + 1];
+    t.a = fmaf(t.w, B.w - A.w, A.w);
+    t.rgb = mk3(fmaf(t.w, B.x - A.x, A.x), fmaf(t.w, B.y - A.y, A.y), fmaf(t.w, B.z - A.z, A.z));
+    if constexpr (MODE == kFrozen) {
+        const float4 C = lut_s[t.l0], D = lut_s[t.l0 + 1];
+        t.a_s = fmaf(t.w, D.w - C.w, C.w);
+    } else {
+        t.a_s = t.a;
+    }
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry
+// ---------------------------------------------------------------------------
+// [tn, tf) of o + t d, t >= 0, inside the box; false when empty.
+__device__ __forceinline__ bool clip_box(const TraceParams& P, f3 o, f3 d, float& tn, float& tf) {
+    float t0 = 0.0f, t1 = 3.402823466e38f;
+    const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dd[a] == 0.0f) {
+            if (oo[a] < P.bmin[a] || oo[a] > P.bmax[a]) return false;
+            continue;
+        }
+        const float inv = 1.0f / dd[a];
+        float ta = (P.bmin[a] - oo[a]) * inv, tb = (P.bmax[a] - oo[a]) * inv;
+        if (ta > tb) {
+            const float t = ta;
+            ta = tb;
+            tb = t;
+        }
+        t0 = fmaxf(t0, ta);
+        t1 = fminf(t1, tb);
+    }
+    tn = t0;
+    tf = t1;
+    return t0 < t1;
+}
+
+// Orthonormal completion of unit n (Duff et al. 2017).
+__device__ __forceinline__ void frame(f3 n, f3& t1, f3& t2) {
+    const float sg = n.z >= 0.0f ? 1.0f : -1.0f;
+    const float a = -1.0f / (sg + n.z);
+    const float b = n.x * n.y * a;
+    t1 = mk3(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
+    t2 = mk3(b, sg + n.y * n.y * a, -n.y);
+}
+
+__device__ __forceinline__ float hg_phase(float g, float mu) {
+    const float den = 1.0f + g * g - 2.0f * g * mu;
+    const float r = 1.0f / sqrtf(den);
+    return (1.0f - g * g) * 0.0795774715459476679f * r * r * r;
+}
+__device__ __forceinline__ float hg_mu(float g, float u) {
+    float mu;
+    if (fabsf(g) < 1e-3f) {
+        mu = 1.0f - 2.0f * u;
+    } else {
+        const float s = (1.0f - g * g) / (1.0f - g + 2.0f * g * u);
+        mu = (1.0f + g * g - s * s) / (2.0f * g);
+    }
+    return fminf(fmaxf(mu, -1.0f), 1.0f);
+}
+
+__device__ __forceinline__ float neg_log1m(float u) { return -__logf(1.0f - u); }
+
+// ---------------------------------------------------------------------------
+// Gradient accumulation (kGrad): per-lane cache of the alpha gradient of the
+// last LUT pair, flushed into the workgroup's LDS accumulator when the pair
+// changes; scale gradient kept in a register.
+// ---------------------------------------------------------------------------
+struct GradAcc {
+    float* lds;     // [lut_n][4]
+    int cl0;
+    float c0, c1;
+    float dscale;
+    __device__ __forceinline__ void flush() {
+        if (cl0 >= 0) {
+            atomicAdd(&lds[cl0 * 4 + 3], c0);
+            atomicAdd(&lds[cl0 * 4 + 7], c1);
+        }
+        cl0 = -1;
+        c0 = c1 = 0.0f;
+    }
+    // d(sigma) = scale * ((1-w) d alpha[l0] + w d alpha[l0+1]) + alpha d scale,
+    // scattered with factor f.
+    __device__ __forceinline__ void sigma(const TF& t, float scale, float f) {
+        if (t.l0 != cl0) {
+            flush();
+            cl0 = t.l0;
+        }
+        c0 = fmaf(f * scale, 1.0f - t.w, c0);
+        c1 = fmaf(f * scale, t.w, c1);
+        dscale = fmaf(f, t.a, dscale);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One path sample of ray k = (i, j).  Returns its radiance.  In kGrad mode
+// `ltot` is this sample's radiance from a forward replay and `adj` the
+// adjoint of the texel divided by spp.
+// ---------------------------------------------------------------------------
+template <int VT, int BR, int MODE>
+__device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const float4* lut_s, float sigbar,
+                           float inv_sigbar, uint32_t k, f3 po, f3 dir, uint32_t s, Counters& cnt, f3 ltot,
+                           f3 adj, GradAcc& G) {
+    const uint32_t K0 = P.key0, K1 = P.key1;
+    f3 x = mk3(P.O[0], P.O[1], P.O[2]) + po * P.R;
+    if (P.jitter) {
+        const u4 r = philox(k, s, kPurJitter, 0, K0, K1);
+        const float rho = P.jit_rad * sqrtf(u01(r.x));
+        float sa, ca;
+        sincospif(2.0f * u01(r.y), &sa, &ca);
+        f3 t1, t2;
+        frame(po, t1, t2);
+        x = x + (t1 * (rho * ca) + t2 * (rho * sa));
+    }
+    f3 T = mk3(1.0f, 1.0f, 1.0f);
+    float W = 1.0f;
+    f3 L = mk3(0.0f, 0.0f, 0.0f);
+    const f3 env = mk3(P.env[0], P.env[1], P.env[2]);
+    cnt.samples++;
+    for (int b = 0; b < P.maxb; ++b) {
+        float tn, tf;
+        const bool hit = clip_box(P, x, dir, tn, tf);
+        bool real = false;
+        f3 y = x;
+        TF te;
+        te.l0 = 0;
+        te.w = 0.0f;
+        te.a = 0.0f;
+        te.a_s = 0.0f;
+        te.rgb = mk3(0.0f, 0.0f, 0.0f);
+        if (hit && sigbar > 0.0f) {
+            const uint32_t c2 = ((uint32_t)b << 8) | kPurFlight;
+            float t = tn;
+            bool done = false;
+            for (uint32_t blk = 0; blk < kMaxFlightBlocks; ++blk) {
+                const u4 r = philox(k, s, c2, blk, K0, K1);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t ud = h ? r.z : r.x, ua = h ? r.w : r.y;
+                    t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
+                    if (t >= tf) {
+                        done = true;
+                        break;
+                    }
+                    cnt.tent++;
+                    y = fma3(dir, t, x);
+                    te = classify<MODE>(P, lut_e, lut_s, sample_volume<VT, BR>(P, y));
+                    const float sig_e = P.scale_e * te.a;
+                    const float sig_s = MODE == kFrozen ? P.scale_s * te.a_s : sig_e;
+                    if (u01(ua) * sigbar < sig_s) {
+                        real = true;
+                        done = true;
+                        if constexpr (MODE == kFrozen) W *= sig_e / sig_s;
+                        if constexpr (MODE == kGrad) G.sigma(te, P.scale_e, dot(adj, ltot - L) / sig_e);
+                        break;
+                    }
+                    if constexpr (MODE == kFrozen) W *= (sigbar - sig_e) / (sigbar - sig_s);
+                    if constexpr (MODE == kGrad) G.sigma(te, P.scale_e, -dot(adj, ltot - L) / (sigbar - sig_e));
+                }
+                if (done) break;
+            }
+            if (!done) return L;  // step cap reached: absorbed
+        }
+        if (!real) {
+            L = L + T * env * W;
+            return L;
+        }
+        cnt.real++;
+        x = y;
+        const f3 rho = mk3(fminf(fmaxf(te.rgb.x, 0.0f), 1.0f), fminf(fmaxf(te.rgb.y, 0.0f), 1.0f),
+                           fminf(fmaxf(te.rgb.z, 0.0f), 1.0f));
+        if constexpr (MODE == kGrad) {
+            // albedo scores d rho_c / rho_c times the channel's later radiance
+            const f3 after = (ltot - L) * adj;
+            const float ra[3] = {te.rgb.x, te.rgb.y, te.rgb.z};
+            const float af[3] = {after.x, after.y, after.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (ra[c] > 0.0f && ra[c] < 1.0f && af[c] != 0.0f) {
+                    const float f = af[c] / ra[c];
+                    atomicAdd(&G.lds[te.l0 * 4 + c], f * (1.0f - te.w));
+                    atomicAdd(&G.lds[te.l0 * 4 + 4 + c], f * te.w);
+                }
+        }
+        T = T * rho;
+        if (T.x == 0.0f && T.y == 0.0f && T.z == 0.0f) return L;
+        const u4 rv = philox(k, s, ((uint32_t)b << 8) | kPurVertex, 0, K0, K1);
+        if (P.light_on) {
+            f3 om;
+            f3 Le;
+            float tend = 0.0f;
+            if (P.light_kind == 0) {
+                om = mk3(P.ldir[0], P.ldir[1], P.ldir[2]);
+                Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]);
+                float a0, a1;
+                if (clip_box(P, x, om, a0, a1)) tend = a1;
+            } else {
+                const f3 yl = mk3(P.lcorner[0], P.lcorner[1], P.lcorner[2]) +
+                              mk3(P.le1[0], P.le1[1], P.le1[2]) * u01(rv.x) +
+                              mk3(P.le2[0], P.le2[1], P.le2[2]) * u01(rv.y);
+                const f3 v = yl - x;
+                const float dist = sqrtf(dot(v, v));
+                om = v * (1.0f / dist);
+                const float cl = fmaxf(0.0f, -dot(mk3(P.lnrm[0], P.lnrm[1], P.lnrm[2]), om));
+                const float f = cl * P.larea / (dist * dist);
+                Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * f;
+                float a0, a1;
+                tend = dist;
+                if (clip_box(P, x, om, a0, a1)) tend = fminf(tend, a1);
+                else tend = 0.0f;
+            }
+            float Tr = 1.0f;
+            if (sigbar > 0.0f) {
+                const uint32_t c2 = ((uint32_t)b << 8) | kPurShadow;
+                float t = 0.0f;
+                bool done = false;
+                for (uint32_t blk = 0; blk < kMaxShadowBlocks; ++blk) {
+                    const u4 r = philox(k, s, c2, blk, K0, K1);
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const uint32_t ud = h == 0 ? r.x : (h == 1 ? r.y : (h == 2 ? r.z : r.w));
+                        t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
+                        if (t >= tend) {
+                            done = true;
+                            break;
+                        }
+                        cnt.shadow++;
+                        const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT, BR>(P, fma3(om, t, x)));
+                        Tr *= 1.0f - P.scale_e * ts.a * inv_sigbar;
+                    }
+                    if (done) break;
+                }
+                if (!done) Tr = 0.0f;  // step cap reached: blocked
+            }
+            const float fp = hg_phase(P.g, dot(dir, om));
+            const f3 C = T * Le * (W * fp * Tr);
+            if constexpr (MODE == kGrad) {
+                // ratio-tracking scores -d sigma / (sigma_bar - sigma) times this
+                // NEE term only: replay the shadow steps now that Tr is known
+                const float rc = dot(adj, C);
+                if (rc != 0.0f && sigbar > 0.0f) {
+                    const uint32_t c2 = ((uint32_t)b << 8) | kPurShadow;
+                    float t = 0.0f;
+                    for (uint32_t blk = 0; blk < kMaxShadowBlocks; ++blk) {
+                        const u4 r = philox(k, s, c2, blk, K0, K1);
+                        bool done = false;
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            const uint32_t ud = h == 0 ? r.x : (h == 1 ? r.y : (h == 2 ? r.z : r.w));
+                            t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
+                            if (t >= tend) {
+                                done = true;
+                                break;
+                            }
+                            const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT, BR>(P, fma3(om, t, x)));
+                            G.sigma(ts, P.scale_e, -rc / (sigbar - P.scale_e * ts.a));
+                        }
+                        if (done) break;
+                    }
+                }
+            }
+            L = L + C;
+        }
+        if (b == P.maxb - 1) return L;
+        const float mu = hg_mu(P.g, u01(rv.z));
+        const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+        float sp, cp;
+        sincospif(2.0f * u01(rv.w), &sp, &cp);
+        f3 t1, t2;
+        frame(dir, t1, t2);
+        dir = t1 * (st * cp) + t2 * (st * sp) + dir * mu;
+    }
+    return L;
+}
+
+}  // namespace lp

@@ -1,0 +1,401 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars:
+  - point coordinates: within 4e-7 of the FP64 values (FP32 rounding);
+  - indices (nearest point, neighbour sets): bit-exact wherever the oracle's
+    decision margin exceeds the FP32 band; inside the band the GPU's choice
+    must be one of the near-tied candidates;
+  - radiance: aggregate relative L1 error <= 1e-3 with the same random stream;
+  - lookup RGB: <= 2e-5 relative (plus 1e-7 absolute) on decided pixels.
+Inputs are seeded synthetic scenes (lfsynth) or seeded random light fields,
+never outputs of the GPU path.
+"""
+import dataclasses
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lfsynth as S
+
+pytestmark = pytest.mark.gpu
+
+RAD_TOL = 1e-3
+# FP32 band of the nearest / K-th decisions, relative to the area per point
+BAND = 1e-4
+
+
+@pytest.fixture(scope="module")
+def lp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1903_03837_amd as lp
+    lp.library()
+    return lp
+
+
+def rel_l1(got, ref):
+    return float(np.abs(got - ref).sum() / np.abs(ref).sum())
+
+
+def nondegenerate(M, N, ks):
+    ks = np.asarray(ks)
+    return ks[~((M == N) & ((ks // N) == (ks % N)))]
+
+
+def gpu_field(lp, sc, dtype="f32", sample=None, stats=False):
+    vol, med, light, prm, _ = lp.device_scene(sc)
+    st = torch.zeros(4, dtype=torch.int64, device="cuda") if stats else None
+    smp = None
+    if sample is not None:
+        smp = lp.Medium(torch.from_numpy(sample.lut).cuda(), sample.scale)
+    lf = lp.generate(vol, med, light, prm, dtype=dtype, sample=smp, stats=st)
+    torch.cuda.synchronize()
+    out = lf.float().reshape(-1, 3).cpu().numpy().astype(np.float64)
+    return (out, st.cpu().numpy()) if stats else out
+
+
+# ------------------------------------------------------------------ SF points
+@pytest.mark.parametrize("n", [1, 2, 5, 256, 2048, 32768, 65535])
+def test_points(lp, orc, n):
+    xyz, _, _ = lp.points(n)
+    torch.cuda.synchronize()
+    got = xyz.cpu().numpy().astype(np.float64)
+    ref = orc.sf_points(n)
+    assert np.abs(got - ref).max() < 4e-7
+
+
+def unit_queries(n_rand, seed, extra=()):
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal((n_rand, 3))
+    q = np.concatenate([q, np.array([[0, 0, 1.0], [0, 0, -1.0], [-1.0, 1e-7, 0.0], [-1.0, -1e-7, 0.3]])] +
+                       [np.asarray(e) for e in extra])
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return q.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [16, 256, 2048, 8192, 32768])
+def test_neighbor_query(lp, orc, n):
+    P = orc.sf_points(n)
+    rng = np.random.default_rng(n)
+    # every point itself, points jittered by 0.3 spacings, random queries, poles, seam
+    pts = P[rng.choice(n, min(n, 2000), replace=False)]
+    jit = pts + 0.3 * math.sqrt(4 * math.pi / n) * rng.standard_normal(pts.shape)
+    q = unit_queries(6000, n + 1, extra=(pts, jit))
+    K = 5
+    _, idx, w = lp.points(n, torch.from_numpy(q).cuda(), K, want_xyz=False)
+    torch.cuda.synchronize()
+    g_idx = idx.cpu().numpy()
+    g_w = w.cpu().numpy()
+    o_idx, o_w, o_d2, mg, cnt = orc.neighbors_batch(n, q.astype(np.float64), K)
+    area = 4 * math.pi / n
+    clear = (mg[:, 0] / area > BAND) & (mg[:, 1] > 1e-3) & (mg[:, 2] / area > BAND)
+    assert clear.mean() > 0.99
+    assert np.array_equal(g_idx[clear], o_idx[clear])
+    assert np.abs(g_w[clear] - o_w[clear]).max() < 1e-4
+    # near-tied nearest: the GPU's pick is within the band of the best
+    amb = ~clear
+    if amb.any():
+        Pq = P[np.clip(g_idx[amb, 0], 0, n - 1)]
+        d_gpu = np.sum((Pq - q[amb].astype(np.float64)) ** 2, 1)
+        assert np.all(d_gpu - o_d2[amb, 0] <= BAND * area)
+
+
+# ------------------------------------------------------------------ generation
+def test_generate_c1_full(lp, orc):
+    """Tiny blob workload at full size: all 65,536 rays against the oracle."""
+    sc = S.config(1)
+    got, st = gpu_field(lp, sc, stats=True)
+    ks = np.arange(256 * 256)
+    ref, ost = orc.generate(sc, ks, stats=True)
+    assert np.all(got[ks[(ks // 256) == (ks % 256)]] == 0.0)
+    nd = nondegenerate(256, 256, ks)
+    err = rel_l1(got[nd], ref[nd])
+    flips = int((np.abs(got[nd] - ref[nd]).max(1) > 1e-2 * np.maximum(ref[nd].max(1), 1e-3)).sum())
+    print(f"c1: rel L1 {err:.3e}, flip texels {flips}, collisions/sample GPU {st[0] / st[3]:.3f} "
+          f"oracle {ost[0] / ost[3]:.3f}")
+    assert err <= RAD_TOL
+    assert st[3] == ost[3]
+    assert abs(st[0] / ost[0] - 1) < 1e-3 and abs(st[1] / ost[1] - 1) < 1e-3
+
+
+def test_generate_c5_subset(lp, orc):
+    """Differentiation workload (f32 volume), 4000 sampled rays."""
+    sc = S.config(5)
+    got = gpu_field(lp, sc)
+    ks = S.random_rays(1024, 1024, 4000, 55)
+    ref = orc.generate(sc, ks)
+    assert rel_l1(got[ks], ref) <= RAD_TOL
+
+
+def test_generate_c2_full_size_sampled(lp, orc):
+    """CT-like workload at full size (4.19M rays, 64 spp, 8 bounces, area
+    light), in the configuration the benchmark times; 1500 sampled rays."""
+    sc = S.config(2)
+    got = gpu_field(lp, sc)
+    ks = S.random_rays(2048, 2048, 1500, 22)
+    ref = orc.generate(sc, ks)
+    err = rel_l1(got[ks], ref)
+    print(f"c2 sampled rel L1 {err:.3e}")
+    assert err <= RAD_TOL
+    assert np.all(np.isfinite(got))
+
+
+def test_generate_ragged_and_tiny(lp, orc):
+    """Sizes that are not multiples of the 8 x 8 tile, M != N, M = N = 1."""
+    for M, N in [(13, 7), (1, 1), (3, 40), (37, 37)]:
+        sc = S.config(1, M=M, N=N, spp=4)
+        got = gpu_field(lp, sc)
+        ks = np.arange(M * N)
+        ref = orc.generate(sc, ks)
+        nd = nondegenerate(M, N, ks)
+        if M == N:
+            assert np.all(got[ks[(ks // N) == (ks % N)]] == 0.0)
+        if len(nd) and np.abs(ref[nd]).sum() > 0:
+            assert rel_l1(got[nd], ref[nd]) <= RAD_TOL, (M, N)
+
+
+def test_row_slabs_bit_identical(lp):
+    sc = S.config(1, M=64, N=64, spp=4)
+    vol, med, light, prm, _ = lp.device_scene(sc)
+    full = lp.generate(vol, med, light, prm)
+    part = torch.zeros_like(full)
+    for a, b in [(0, 21), (21, 22), (22, 64)]:
+        lp.generate(vol, med, light, dataclasses.replace(prm, row_begin=a, row_end=b), out=part)
+    torch.cuda.synchronize()
+    assert torch.equal(full, part)
+
+
+def test_bricked_equals_linear(lp, orc):
+    """The 8^3 brick-major layout reads exactly the same voxels."""
+    v = S.phantom_volume(64, 1234, 8)
+    lin = S.Volume(v.reshape(-1), S.U16, (64, 64, 64), 0, 24.0, 3024.0)
+    brk = S.Volume(S.brick_layout(v, 8), S.U16, (64, 64, 64), 8, 24.0, 3024.0)
+    sc = S.config(2, M=128, N=128, spp=4)
+    a = gpu_field(lp, sc.replace(volume=lin))
+    b = gpu_field(lp, sc.replace(volume=brk))
+    assert np.array_equal(a, b)
+    ks = S.random_rays(128, 128, 1500, 3)
+    ref = orc.generate(sc.replace(volume=brk), ks)
+    assert rel_l1(b[ks], ref) <= RAD_TOL
+
+
+def test_white_furnace(lp):
+    sc = S.config(1, M=64, N=64, spp=8, max_bounces=1000)
+    lut = sc.medium.lut.copy()
+    lut[:, :3] = 1.0
+    sc = sc.replace(medium=S.Medium(lut, 40.0),
+                    light=dataclasses.replace(sc.light, radiance=(0, 0, 0), env=(1.0, 1.0, 1.0)))
+    got = gpu_field(lp, sc)
+    ks = np.arange(64 * 64)
+    assert np.all(got[nondegenerate(64, 64, ks)] == 1.0)
+
+
+def test_vacuum_and_linearity(lp):
+    sc = S.config(1, M=32, N=32, spp=4)
+    vac = gpu_field(lp, sc.replace(medium=S.Medium(sc.medium.lut, 0.0),
+                                   light=dataclasses.replace(sc.light, env=(0.25, 0.5, 1.0))))
+    nd = nondegenerate(32, 32, np.arange(32 * 32))
+    assert np.all(vac[nd] == np.array([0.25, 0.5, 1.0]))
+    a = gpu_field(lp, sc)
+    b = gpu_field(lp, sc.replace(light=dataclasses.replace(sc.light, radiance=(2.0, 2.0, 2.0))))
+    assert np.array_equal(b, 2 * a)
+
+
+@pytest.mark.parametrize("dtype,bound", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_half_storage(lp, orc, dtype, bound):
+    """FP16/BF16 storage rounds the FP32 mean once (round to nearest even)."""
+    sc = S.config(1)
+    f32 = gpu_field(lp, sc)
+    low = gpu_field(lp, sc, dtype=dtype)
+    nz = f32 > (6.2e-5 if dtype == "f16" else 1e-30)
+    assert np.all(np.abs(low[nz] - f32[nz]) <= bound * np.abs(f32[nz]))
+    ref_dt = torch.tensor(f32.astype(np.float32)).to(torch.float16 if dtype == "f16" else torch.bfloat16)
+    assert np.array_equal(low.astype(np.float32), ref_dt.float().numpy())
+    ks = nondegenerate(256, 256, S.random_rays(256, 256, 3000, 8))
+    ref = orc.generate(sc, ks)
+    print(f"{dtype}: rel L1 vs FP64 oracle {rel_l1(low[ks], ref):.3e} (FP32: {rel_l1(f32[ks], ref):.3e})")
+
+
+def test_frozen_sampling(lp, orc):
+    sc = S.config(1, M=64, N=64, spp=8)
+    base = gpu_field(lp, sc)
+    same = gpu_field(lp, sc, sample=S.Medium(sc.medium.lut.copy(), sc.medium.scale))
+    assert np.array_equal(base, same)  # all weights are exactly 1 at theta_0
+    sig = orc.majorant(sc.medium, sc.params)
+    sc_fixed = sc.with_params(majorant=sig)
+    pert = S.Medium(np.clip(sc.medium.lut + 0.05, 0, 1).astype(np.float32), sc.medium.scale * 1.1)
+    got = gpu_field(lp, sc_fixed.replace(medium=pert), sample=sc.medium)
+    ks = nondegenerate(64, 64, np.arange(64 * 64))
+    ref = orc.generate(sc_fixed.replace(medium=pert), ks, sample_medium=sc.medium)
+    assert rel_l1(got[ks], ref) <= RAD_TOL
+
+
+# ------------------------------------------------------------------ lookup
+def lookup_case(lp, orc, M, N, views, W, H, K, dtype="f32", seed=0, pix=None):
+    rng = np.random.default_rng(seed)
+    lf32 = rng.uniform(0.0, 1.0, (M, N, 3)).astype(np.float32)
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    lf = torch.from_numpy(lf32).to(tdt).cuda()
+    sc = S.config(2, M=M, N=N, views=views, width=W, height=H)
+    prm = lp.GenParams(M=M, N=N, radius=sc.params.radius)
+    cams = [lp.Camera(c.eye, c.target, c.up, c.vfov) for c in sc.cams]
+    img, nn = lp.lookup(lf, prm, cams, W, H, K=K, with_nn=True)
+    torch.cuda.synchronize()
+    g_img = img.reshape(-1, 3).cpu().numpy()
+    g_nn = nn.reshape(-1, 2).cpu().numpy()
+    if pix is None:
+        pix = orc.all_pixels(views, W, H)
+    flat = (pix[:, 0].astype(np.int64) * H + pix[:, 2]) * W + pix[:, 1]
+    rgb, onn, mg = orc.lookup(lf.float().cpu().numpy(), sc.params, sc.cams, W, H, K, pix)
+    clear = (mg[:, 0] > 1e-4) & (mg[:, 1] > BAND) & (mg[:, 2] > 1e-3) & ((mg[:, 3] > BAND) | (K == 1))
+    return g_img[flat], g_nn[flat], rgb, onn, clear
+
+
+@pytest.mark.parametrize("K", [1, 5, 9])
+def test_lookup_small(lp, orc, K):
+    g_img, g_nn, rgb, onn, clear = lookup_case(lp, orc, 256, 256, 3, 72, 40, K)
+    print(f"K={K}: {(~clear).sum()} of {len(clear)} pixels inside a decision band")
+    assert clear.mean() > 0.995
+    assert np.array_equal(g_nn[clear], onn[clear])
+    assert np.all(np.abs(g_img[clear] - rgb[clear]) <= 2e-5 * np.abs(rgb[clear]) + 1e-7)
+    hit = onn[:, 0] >= 0
+    assert np.all(g_img[clear & ~hit] == 0.0) and np.all(g_nn[clear & ~hit] == -1)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_lookup_half_storage(lp, orc, dtype):
+    g_img, g_nn, rgb, onn, clear = lookup_case(lp, orc, 200, 180, 2, 48, 36, 5, dtype=dtype, seed=3)
+    assert np.array_equal(g_nn[clear], onn[clear])
+    assert np.all(np.abs(g_img[clear] - rgb[clear]) <= 2e-5 * np.abs(rgb[clear]) + 1e-7)
+
+
+def test_lookup_c2_full_size_sampled(lp, orc):
+    """32 views of 1920 x 1080 over an N = 2048 light field (the benchmark's
+    lookup), checked on 6000 sampled pixels."""
+    rng = np.random.default_rng(9)
+    V, W, H = 32, 1920, 1080
+    pix = np.stack([rng.integers(0, V, 6000), rng.integers(0, W, 6000), rng.integers(0, H, 6000)], 1)
+    g_img, g_nn, rgb, onn, clear = lookup_case(lp, orc, 2048, 2048, V, W, H, 5, pix=pix.astype(np.int32))
+    assert clear.mean() > 0.99
+    assert np.array_equal(g_nn[clear], onn[clear])
+    assert np.all(np.abs(g_img[clear] - rgb[clear]) <= 2e-5 * np.abs(rgb[clear]) + 1e-7)
+
+
+def test_lookup_adjoint(lp, orc):
+    M, N, V, W, H, K = 96, 80, 2, 40, 30, 5
+    sc = S.config(1, M=M, N=N, views=V, width=W, height=H)
+    prm = lp.GenParams(M=M, N=N, radius=sc.params.radius)
+    cams = [lp.Camera(c.eye, c.target, c.up, c.vfov) for c in sc.cams]
+    rng = np.random.default_rng(4)
+    dimg = rng.standard_normal((V, H, W, 3)).astype(np.float32)
+    d_lf = lp.lookup_adjoint(torch.from_numpy(dimg).cuda(), prm, cams, K)
+    torch.cuda.synchronize()
+    pix = orc.all_pixels(V, W, H)
+    flat = (pix[:, 0].astype(np.int64) * H + pix[:, 2]) * W + pix[:, 1]
+    ref = orc.lookup_adjoint(sc.params, sc.cams, W, H, K, pix, dimg.reshape(-1, 3)[flat].astype(np.float64))
+    got = d_lf.reshape(-1).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------------------------ adjoint
+def grad_scene():
+    sc = S.config(1, M=48, N=48, spp=6, max_bounces=3, g=0.3)
+    lut = (0.05 + 0.9 * sc.medium.lut).astype(np.float32)
+    lut[0, 3] = 0.0
+    return sc.replace(medium=S.Medium(lut, 25.0), light=dataclasses.replace(sc.light, env=(0.3, 0.2, 0.1)))
+
+
+def test_backward_matches_oracle_gradient(lp, orc):
+    sc = grad_scene()
+    M = N = 48
+    rng = np.random.default_rng(12)
+    ks = nondegenerate(M, N, S.random_rays(M, N, 600, 7))
+    adj = rng.standard_normal((len(ks), 3))
+    d_lf = np.zeros((M * N, 3), np.float32)
+    d_lf[ks] = adj
+    vol, med, light, prm, _ = lp.device_scene(sc)
+    d_lut, d_scale = lp.generate_backward(vol, med, light, prm, torch.from_numpy(d_lf).cuda())
+    torch.cuda.synchronize()
+    g_lut = d_lut.cpu().numpy().astype(np.float64)
+    o_lut, o_scale = orc.gradient(sc, ks, d_lf[ks].astype(np.float64))
+    err = np.linalg.norm(g_lut - o_lut) / np.linalg.norm(o_lut)
+    print(f"adjoint vs oracle gradient: {err:.2e}, dscale {float(d_scale[0]):.6g} vs {o_scale:.6g}")
+    assert err <= 1e-3
+    assert abs(float(d_scale[0]) - o_scale) <= 1e-3 * abs(o_scale)
+
+
+def test_backward_matches_finite_differences(lp, orc):
+    """Central differences (h = 1e-3) of the GPU forward in frozen sampling."""
+    sc = grad_scene()
+    M = N = 48
+    sig = orc.majorant(sc.medium, sc.params)
+    sc = sc.with_params(majorant=sig)
+    rng = np.random.default_rng(13)
+    adj = rng.standard_normal((M * N, 3))
+    adj[np.arange(M) * (N + 1)] = 0.0
+    vol, med, light, prm, _ = lp.device_scene(sc)
+    d_lut, d_scale = lp.generate_backward(vol, med, light, prm, torch.from_numpy(adj.astype(np.float32)).cuda())
+    g = np.concatenate([d_lut.cpu().numpy().reshape(-1), d_scale.cpu().numpy()]).astype(np.float64)
+    theta0 = sc.medium
+    smp = lp.Medium(torch.from_numpy(theta0.lut).cuda(), theta0.scale)
+
+    def loss(lut, scale):
+        m = lp.Medium(torch.from_numpy(lut).cuda(), scale)
+        L = lp.generate(vol, m, light, prm, sample=smp).double().cpu().numpy().reshape(-1, 3)
+        return float((L * adj).sum())
+
+    h = 1e-3
+    fd = np.zeros_like(g)
+    touched = np.argwhere(np.abs(g[:-1].reshape(-1, 4)) > 1e-4 * np.abs(g).max())
+    for e, c in touched:
+        lp_, lm = theta0.lut.copy(), theta0.lut.copy()
+        lp_[e, c] += h
+        lm[e, c] -= h
+        fd[4 * e + c] = (loss(lp_, theta0.scale) - loss(lm, theta0.scale)) / (float(lp_[e, c]) - float(lm[e, c]))
+    fd[-1] = (loss(theta0.lut, theta0.scale + h) - loss(theta0.lut, theta0.scale - h)) / (2 * h)
+    mask = np.zeros_like(g, bool)
+    mask[[4 * e + c for e, c in touched]] = True
+    mask[-1] = True
+    err = np.linalg.norm(fd[mask] - g[mask]) / np.linalg.norm(g[mask])
+    print(f"adjoint vs central differences on {mask.sum()} coordinates: {err:.2e}")
+    assert err <= 1e-2
+
+
+def test_autograd_pipeline(lp, orc):
+    """Differentiation workload, reduced: LightFieldFn -> LookupFn -> L2 loss;
+    the LUT gradient equals the oracle's chain (lookup transpose, then the
+    path-replay gradient) on the same views."""
+    M = N = 64
+    V, W, H, K = 3, 48, 40, 5
+    sc = S.config(5, M=M, N=N, spp=8, views=V, width=W, height=H)
+    vol, med, light, prm, cams = lp.device_scene(sc)
+    tgt = S.target_medium(sc)
+    # targets and their oracle counterparts from the oracle's own forward
+    ks = np.arange(M * N)
+    lf_t = orc.generate(sc.replace(medium=tgt), ks).astype(np.float32)
+    pix = orc.all_pixels(V, W, H)
+    flat = (pix[:, 0].astype(np.int64) * H + pix[:, 2]) * W + pix[:, 1]
+    t_rgb, _, _ = orc.lookup(lf_t, sc.params, sc.cams, W, H, K, pix)
+    target = np.zeros((V * H * W, 3), np.float32)
+    target[flat] = t_rgb
+    lut = med.lut.clone().requires_grad_(True)
+    scale = torch.tensor(float(med.scale), requires_grad=True)
+    lf = lp.LightFieldFn.apply(lut, scale, vol, light, prm)
+    img = lp.LookupFn.apply(lf, prm, cams, W, H, K)
+    loss = ((img - torch.from_numpy(target.reshape(V, H, W, 3)).cuda()) ** 2).sum()
+    loss.backward()
+    g_lut = lut.grad.cpu().numpy().astype(np.float64)
+    # oracle chain
+    lf_o = orc.generate(sc, ks)
+    o_rgb, _, _ = orc.lookup(lf_o.astype(np.float32), sc.params, sc.cams, W, H, K, pix)
+    dimg = 2 * (o_rgb - target[flat])
+    d_lf = orc.lookup_adjoint(sc.params, sc.cams, W, H, K, pix, dimg).reshape(-1, 3)
+    rows = np.nonzero(np.abs(d_lf).sum(1))[0]
+    o_lut, o_scale = orc.gradient(sc, rows, d_lf[rows])
+    err = np.linalg.norm(g_lut - o_lut) / np.linalg.norm(o_lut)
+    print(f"pipeline gradient vs oracle chain: {err:.2e}; dscale {float(scale.grad):.5g} vs {o_scale:.5g}")
+    assert err <= 1e-2
+    assert abs(float(scale.grad) - o_scale) <= 1e-2 * abs(o_scale)
