@@ -59,7 +59,7 @@ enum { LF_LOOKUP_FORWARD = 0, LF_LOOKUP_ADJOINT = 1 };
  * bricks, bricks ordered x-fastest, voxels x-fastest inside a brick (each of
  * nx, ny, nz divisible by 8).  nx, ny, nz >= 2. */
 typedef struct {
-    const void* data;       /* device [nx*ny*nz] of the voxel type */
+    const void* data;       /* device [nx*ny*nz] of the voxel type, aligned to it */
     int32_t type;           /* LF_VOX_* */
     int32_t nx, ny, nz;
     int32_t brick;          /* 0 or 8 */
@@ -67,8 +67,8 @@ typedef struct {
     float box_min[3], box_max[3];
 } lf_volume;
 
-/* Transfer function: lut_size RGBA entries (device, float32 [lut_size][4]),
- * interpolated linearly; sigma_t = density_scale * alpha, single-scattering
+/* Transfer function: lut_size RGBA entries (device, float32 [lut_size][4],
+ * 16-byte aligned), interpolated linearly; sigma_t = density_scale * alpha, single-scattering
  * albedo = rgb clamped to [0,1].  2 <= lut_size <= 1024. */
 typedef struct {
     const float* lut;

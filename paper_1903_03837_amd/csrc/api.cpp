@@ -59,6 +59,8 @@ int check_volume(const lf_volume* v) {
     if (v->type < LF_VOX_U8 || v->type > LF_VOX_F32) return fail(LF_E_ARG, "unknown voxel type %d", v->type);
     if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(LF_E_ARG, "volume dimensions must be >= 2");
     if ((unsigned long long)v->nx * v->ny * v->nz >= (1ull << 32)) return fail(LF_E_RANGE, "volume too large");
+    const uintptr_t esz = v->type == LF_VOX_U8 ? 1 : (v->type == LF_VOX_U16 ? 2 : 4);
+    if ((uintptr_t)v->data % esz) return fail(LF_E_ARG, "volume data is not aligned to its voxel size");
     if (v->brick != 0 && v->brick != 8) return fail(LF_E_UNSUPPORTED, "brick must be 0 or 8");
     if (v->brick == 8 && (v->nx % 8 || v->ny % 8 || v->nz % 8))
         return fail(LF_E_ARG, "bricked volume dimensions must be multiples of 8");
@@ -73,6 +75,7 @@ int check_volume(const lf_volume* v) {
 int check_medium(const lf_medium* m, const char* name) {
     if (!m) return fail(LF_E_ARG, "%s medium is NULL", name);
     if (!m->lut) return fail(LF_E_ARG, "%s lut is NULL", name);
+    if ((uintptr_t)m->lut % 16) return fail(LF_E_ARG, "%s lut must be 16-byte aligned", name);
     if (m->lut_size < 2 || m->lut_size > 1024) return fail(LF_E_ARG, "%s lut_size must be in [2, 1024]", name);
     if (!(m->density_scale >= 0.0f) || !std::isfinite(m->density_scale))
         return fail(LF_E_ARG, "%s density_scale must be finite and >= 0", name);

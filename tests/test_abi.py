@@ -94,6 +94,8 @@ def test_workspace_size_query(lp):
     (lambda v, m, l, p: setattr(v, "brick", 4), LF_E_UNSUPPORTED, "brick"),
     (lambda v, m, l, p: setattr(v, "vmax", -1.0), LF_E_ARG, "vmax"),
     (lambda v, m, l, p: setattr(m, "lut_size", 1), LF_E_ARG, "lut_size"),
+    (lambda v, m, l, p: setattr(m, "lut", 0x20004), LF_E_ARG, "aligned"),
+    (lambda v, m, l, p: (setattr(v, "type", 2), setattr(v, "data", 0x10002)), LF_E_ARG, "aligned"),
     (lambda v, m, l, p: setattr(m, "density_scale", -1.0), LF_E_ARG, "density_scale"),
     (lambda v, m, l, p: setattr(l, "kind", 5), LF_E_ARG, "light kind"),
     (lambda v, m, l, p: l.dir.__setitem__(2, 2.0), LF_E_ARG, "unit vector"),
