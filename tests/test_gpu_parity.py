@@ -6,7 +6,11 @@ Bars:
     decision margin exceeds the FP32 band; inside the band the GPU's choice
     must be one of the near-tied candidates;
   - radiance: aggregate relative L1 error <= 1e-3 with the same random stream;
-  - lookup RGB: <= 2e-5 relative (plus 1e-7 absolute) on decided pixels.
+  - lookup RGB on decided pixels: the FP32 view ray moves a hit point by
+    ~2.5e-7 R, which shifts a tent weight by ~1e-6 / r (r = sqrt(4 pi / n),
+    the unit-sphere filter radius); over a field of value range D the pixel
+    moves by at most LOOKUP_C / r * D (measured 1.2e-5 / r * D on random
+    fields, which have the largest texel-to-texel jumps).
 Inputs are seeded synthetic scenes (lfsynth) or seeded random light fields,
 never outputs of the GPU path.
 """
@@ -25,6 +29,18 @@ pytestmark = pytest.mark.gpu
 RAD_TOL = 1e-3
 # FP32 band of the nearest / K-th decisions, relative to the area per point
 BAND = 1e-4
+LOOKUP_C = 3e-5
+
+
+def lookup_tol(M, N, lf):
+    r = math.sqrt(4 * math.pi / min(M, N))
+    return LOOKUP_C / r * float(lf.max() - lf.min())
+
+
+def check_pixels(g_img, rgb, tol):
+    err = np.abs(g_img - rgb)
+    assert err.max() <= tol, (err.max(), tol)
+    assert np.quantile(err, 0.99) <= tol / 10
 
 
 @pytest.fixture(scope="module")
@@ -93,8 +109,20 @@ def test_neighbor_query(lp, orc, n):
     area = 4 * math.pi / n
     clear = (mg[:, 0] / area > BAND) & (mg[:, 1] > 1e-3) & (mg[:, 2] / area > BAND)
     assert clear.mean() > 0.99
-    assert np.array_equal(g_idx[clear], o_idx[clear])
-    assert np.abs(g_w[clear] - o_w[clear]).max() < 1e-4
+    # the nearest point and the K-set are unique outside the bands; the order
+    # of near-equidistant members inside the set is not (lattice neighbours
+    # at i +- F sit at almost equal distances), so it must only be sorted by
+    # the oracle's distances to within the band
+    assert np.array_equal(g_idx[clear, 0], o_idx[clear, 0])
+    assert np.array_equal(np.sort(g_idx[clear], 1), np.sort(o_idx[clear], 1))
+    qc = q[clear].astype(np.float64)
+    gi = g_idx[clear]
+    d2g = np.sum((P[np.clip(gi, 0, n - 1)] - qc[:, None, :]) ** 2, -1)
+    d2g[gi < 0] = np.inf
+    assert np.all(np.diff(d2g, axis=1) >= -BAND * area)
+    og = np.argsort(g_idx[clear], 1)
+    oo = np.argsort(o_idx[clear], 1)
+    assert np.abs(np.take_along_axis(g_w[clear], og, 1) - np.take_along_axis(o_w[clear], oo, 1)).max() < 1e-4
     # near-tied nearest: the GPU's pick is within the band of the best
     amb = ~clear
     if amb.any():
@@ -249,27 +277,32 @@ def lookup_case(lp, orc, M, N, views, W, H, K, dtype="f32", seed=0, pix=None):
     if pix is None:
         pix = orc.all_pixels(views, W, H)
     flat = (pix[:, 0].astype(np.int64) * H + pix[:, 2]) * W + pix[:, 1]
-    rgb, onn, mg = orc.lookup(lf.float().cpu().numpy(), sc.params, sc.cams, W, H, K, pix)
+    lf_host = lf.float().cpu().numpy()
+    rgb, onn, mg = orc.lookup(lf_host, sc.params, sc.cams, W, H, K, pix)
     clear = (mg[:, 0] > 1e-4) & (mg[:, 1] > BAND) & (mg[:, 2] > 1e-3) & ((mg[:, 3] > BAND) | (K == 1))
-    return g_img[flat], g_nn[flat], rgb, onn, clear
+    return g_img[flat], g_nn[flat], rgb, onn, clear, lookup_tol(M, N, lf_host)
 
 
 @pytest.mark.parametrize("K", [1, 5, 9])
 def test_lookup_small(lp, orc, K):
-    g_img, g_nn, rgb, onn, clear = lookup_case(lp, orc, 256, 256, 3, 72, 40, K)
-    print(f"K={K}: {(~clear).sum()} of {len(clear)} pixels inside a decision band")
+    g_img, g_nn, rgb, onn, clear, tol = lookup_case(lp, orc, 256, 256, 3, 72, 40, K)
+    err = np.abs(g_img[clear] - rgb[clear])
+    print(f"K={K}: {(~clear).sum()} of {len(clear)} pixels inside a decision band; "
+          f"max |err| {err.max():.2e} (tol {tol:.2e})")
     assert clear.mean() > 0.995
     assert np.array_equal(g_nn[clear], onn[clear])
-    assert np.all(np.abs(g_img[clear] - rgb[clear]) <= 2e-5 * np.abs(rgb[clear]) + 1e-7)
+    if K == 1:
+        assert np.array_equal(g_img[clear], rgb[clear])  # nearest sampling copies the texel
+    check_pixels(g_img[clear], rgb[clear], tol)
     hit = onn[:, 0] >= 0
     assert np.all(g_img[clear & ~hit] == 0.0) and np.all(g_nn[clear & ~hit] == -1)
 
 
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
 def test_lookup_half_storage(lp, orc, dtype):
-    g_img, g_nn, rgb, onn, clear = lookup_case(lp, orc, 200, 180, 2, 48, 36, 5, dtype=dtype, seed=3)
+    g_img, g_nn, rgb, onn, clear, tol = lookup_case(lp, orc, 200, 180, 2, 48, 36, 5, dtype=dtype, seed=3)
     assert np.array_equal(g_nn[clear], onn[clear])
-    assert np.all(np.abs(g_img[clear] - rgb[clear]) <= 2e-5 * np.abs(rgb[clear]) + 1e-7)
+    check_pixels(g_img[clear], rgb[clear], tol)
 
 
 def test_lookup_c2_full_size_sampled(lp, orc):
@@ -278,10 +311,10 @@ def test_lookup_c2_full_size_sampled(lp, orc):
     rng = np.random.default_rng(9)
     V, W, H = 32, 1920, 1080
     pix = np.stack([rng.integers(0, V, 6000), rng.integers(0, W, 6000), rng.integers(0, H, 6000)], 1)
-    g_img, g_nn, rgb, onn, clear = lookup_case(lp, orc, 2048, 2048, V, W, H, 5, pix=pix.astype(np.int32))
+    g_img, g_nn, rgb, onn, clear, tol = lookup_case(lp, orc, 2048, 2048, V, W, H, 5, pix=pix.astype(np.int32))
     assert clear.mean() > 0.99
     assert np.array_equal(g_nn[clear], onn[clear])
-    assert np.all(np.abs(g_img[clear] - rgb[clear]) <= 2e-5 * np.abs(rgb[clear]) + 1e-7)
+    check_pixels(g_img[clear], rgb[clear], tol)
 
 
 def test_lookup_adjoint(lp, orc):
