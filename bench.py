@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the LumiPath light-field path on one MI355X.
+
+One step = one pass of the whole path over the CT-like workload (256^3 u16
+phantom, M = N = 2048 spherical-Fibonacci points, 4.19M rays, 64 samples per
+ray, 8 bounces, HG g = 0.3, area light):
+  lf_points (SF table) -> lf_generate (FP32 light field) -> lf_lookup (32 views
+  of 1920 x 1080, K = 5) -> L2 view loss gradient -> lf_lookup adjoint ->
+  lf_generate_backward (d LUT, d density scale).
+`value` = M*N*spp path samples per second of the whole step.  One JSON line
+on stdout; progress on stderr.  Inputs are seeded synthetic data (lfsynth).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic 32-bit ALU operations per unit of work (see the design notes,
+# "roofline of generation"): counted from the estimator's definition, one op
+# per add/mul/fma/compare/convert/logic, four per transcendental, 60 per
+# Philox4x32-10 block (10 rounds x (2 wide multiplies + 4 xor)).
+OPS_TENTATIVE = 113     # free-flight step: 1/2 Philox, log, trilinear fetch, classify, accept
+OPS_SHADOW = 90         # ratio-tracking step: 1/4 Philox, log, trilinear fetch, alpha, Tr update
+OPS_REAL = 270          # scatter vertex: albedo, Philox block, light sample, phase eval/sample, clips
+OPS_SAMPLE = 140        # jitter (Philox block, sqrt, sincos, frame), first clip, escape, accumulate
+OPS_RAY = 80            # two SF points (FP64 frac), direction, store
+PEAK_OPS = 256 * 4 * 16 * 2.4e9   # 32-bit lane ops per second: CUs x SIMDs x lanes x clock
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1903_03837_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_hash):
+    """HBM bytes per generation launch from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "gen_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scene, seconds, nrays_probe=2000):
+    """The FP64 oracle on a bounded seeded sample of the same rays."""
+    import numpy as np
+
+    import lfsynth as S
+    from oracle import oracle as orc
+
+    threads = orc.default_threads()
+    M, N = scene.params.M, scene.params.N
+    ks = S.random_rays(M, N, nrays_probe, 777)
+    t0 = time.perf_counter()
+    orc.generate(scene, ks, nthreads=threads)
+    dt = time.perf_counter() - t0
+    n = int(min(M * N, max(nrays_probe, nrays_probe * seconds / max(dt, 1e-3))))
+    ks = S.random_rays(M, N, n, 778)
+    t0 = time.perf_counter()
+    ref = orc.generate(scene, ks, nthreads=threads)
+    dt = time.perf_counter() - t0
+    samples = len(ks) * scene.params.spp
+    return {"value": samples / dt, "unit": "path samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(ks)} seeded random rays of the same workload x {scene.params.spp} spp "
+                      f"({dt:.1f} s, FP64 C, pthreads)"}, ks, ref
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the light field shards by rows "
+              "of origins; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lfsynth as S
+    import paper_1903_03837_amd as lp
+
+    torch.cuda.set_device(0)
+    lp.library()
+    log("bench: building the CT-like workload (256^3 u16 phantom, N=2048, 64 spp)")
+    sc = S.config(2)
+    vol, med, light, prm, cams = lp.device_scene(sc)
+    V, W, H, K = len(cams), sc.width, sc.height, sc.K
+    M, N, spp = prm.M, prm.N, prm.spp
+    dev = "cuda"
+    lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
+    img = torch.empty((V, H, W, 3), dtype=torch.float32, device=dev)
+    d_lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
+
+    # seeded target views: the same scene under the perturbed medium
+    tm = S.target_medium(sc)
+    tmed = lp.Medium(torch.from_numpy(tm.lut).to(dev), tm.scale)
+    target = lp.lookup(lp.generate(vol, tmed, light, prm), prm, cams, W, H, K)
+
+    # counts of the units of work (deterministic for the fixed stream)
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    lp.generate(vol, med, light, prm, out=lf, stats=stats)
+    torch.cuda.synchronize()
+    tent, shadow, real, samples = (int(x) for x in stats.cpu().numpy())
+    rays = M * N - (M if M == N else 0)
+    alg_ops = (tent * OPS_TENTATIVE + shadow * OPS_SHADOW + real * OPS_REAL + samples * OPS_SAMPLE
+               + rays * OPS_RAY)
+
+    stream = torch.cuda.current_stream()
+    nev = 7
+
+    def step(evs):
+        evs[0].record(stream)
+        lp.points(M)
+        evs[1].record(stream)
+        lp.generate(vol, med, light, prm, out=lf)
+        evs[2].record(stream)
+        lp.lookup(lf, prm, cams, W, H, K, img=img)
+        evs[3].record(stream)
+        dimg = 2.0 * (img - target)
+        evs[4].record(stream)
+        d_lf.zero_()
+        lp.lookup_adjoint(dimg, prm, cams, K, d_lf=d_lf)
+        evs[5].record(stream)
+        d_lut, d_scale = lp.generate_backward(vol, med, light, prm, d_lf)
+        evs[6].record(stream)
+        return d_lut, d_scale
+
+    log(f"bench: {args.warmup} warmup + {args.steps} timed steps")
+    for _ in range(args.warmup):
+        step([torch.cuda.Event(enable_timing=True) for _ in range(nev)])
+    torch.cuda.synchronize()
+    all_evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(all_evs[s])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    legs = {}
+    names = ["points", "generate", "lookup", "loss_grad", "lookup_adjoint", "generate_backward"]
+    for a, name in enumerate(names):
+        legs[name] = float(np.mean([e[a].elapsed_time(e[a + 1]) for e in all_evs]))
+    ms_per_step = elapsed * 1e3 / args.steps
+    log("bench: legs (ms) " + ", ".join(f"{k} {v:.2f}" for k, v in legs.items()))
+
+    gen_s = legs["generate"] / 1e3
+    achieved = alg_ops / gen_s
+    khash = kernel_source_hash()
+    traffic = measured_traffic(khash)
+
+    # storage precision: FP16 / BF16 fields against the FP32 field
+    f32 = lf.clone()
+    f16 = lp.generate(vol, med, light, prm, dtype="f16").float()
+    b16 = lp.generate(vol, med, light, prm, dtype="bf16").float()
+    torch.cuda.synchronize()
+    denom = f32.abs().sum().item()
+    err16 = (f16 - f32).abs().sum().item() / denom
+    errb16 = (b16 - f32).abs().sum().item() / denom
+
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        a_ = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        b_ = torch.empty_like(a_)
+        b_.copy_(a_)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "LF path samples/s + %HBM roofline; FP16 vs FP32 err; adjoint/forward time",
+        "value": M * N * spp / (ms_per_step / 1e3),
+        "unit": "path samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded CT-like phantom, transfer function, area light, cameras)",
+        "config": {
+            "workload": "CT-like phantom 256^3 u16 (12 nested ellipsoids), M=N=2048 SF points (4.19M rays), "
+                        "64 spp, 8 bounces, HG g=0.3, area light, FP32 light field; lookup of 32 views "
+                        "1920x1080 K=5; adjoint of an L2 view loss",
+            "M": M, "N": N, "spp": spp, "max_bounces": prm.max_bounces, "views": V, "width": W, "height": H,
+            "K": K, "volume": "256^3 u16 linear",
+        },
+        "roofline": {
+            "kernel": "gen_kernel (lf_generate)",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_OPS / 1e12,
+            "unit": "Top/s (32-bit lane ops)",
+            "frac": achieved / PEAK_OPS,
+            "traffic": traffic,
+            "launch_ms": legs["generate"],
+            "ops_per_launch": alg_ops,
+            "units_per_launch": {"tentative_collisions": tent, "shadow_steps": shadow, "real_collisions": real,
+                                 "samples": samples, "rays": rays},
+        },
+        "legs_ms": legs,
+        "generate_samples_per_s": M * N * spp / gen_s,
+        "lookup_pixels_per_s": V * W * H / (legs["lookup"] / 1e3),
+        "lookup_gather_GBps": V * W * H * 312 / (legs["lookup"] / 1e3) / 1e9,
+        "adjoint_forward_ratio": legs["generate_backward"] / legs["generate"],
+        "fp16_vs_fp32_rel_err": err16,
+        "bf16_vs_fp32_rel_err": errb16,
+        "collisions_per_sample": tent / samples,
+        "kernel_hash": khash,
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: oracle CPU baseline (~{args.cpu_seconds:.0f} s)")
+        base, ks, ref = cpu_baseline(sc, args.cpu_seconds)
+        out["cpu_baseline"] = base
+        got = f32.reshape(-1, 3)[torch.from_numpy(ks).to(dev)].double().cpu().numpy()
+        got16 = f16.reshape(-1, 3)[torch.from_numpy(ks).to(dev)].double().cpu().numpy()
+        den = np.abs(ref).sum()
+        out["fp32_vs_oracle_rel_err"] = float(np.abs(got - ref).sum() / den)
+        out["fp16_vs_oracle_rel_err"] = float(np.abs(got16 - ref).sum() / den)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -183,14 +183,19 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
 
 double orc_uniform(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
 
-/* Random-number stream of one (ray, sample, bounce, purpose): the counter is
- * (ray, sample, bounce << 8 | purpose, block) and block b supplies the
- * uniforms with stream positions 4b .. 4b+3, word by word. */
-enum { P_JITTER = 0, P_FLIGHT = 1, P_VERTEX = 2, P_SHADOW = 3 };
-/* At most 2^20 tentative collisions per free-flight or shadow segment; a
- * segment that reaches the cap ends absorbed (free flight) or blocked
- * (shadow).  Valid scenes never come near it. */
-#define MAX_STEPS ((int64_t)1 << 20)
+/* Random-number streams.  The counter is (ray, sample, bounce << 8 |
+ * purpose, block) and block b supplies stream positions 4b .. 4b+3, word by
+ * word; positions are used in pairs (pair p = positions 2p, 2p+1).
+ *   purpose 1, "flight" of segment b: at b = 0 pair 0 jitters the origin and
+ *     tentative collision n uses pair n+1; at b > 0 collision n uses pair n.
+ *     A collision pair is (free-flight distance, acceptance).
+ *   purpose 2, "vertex" b: pair 0 samples the light, pair 1 the phase
+ *     function (mu, azimuth); shadow step n uses the first word of pair n+2. */
+enum { P_FLIGHT = 1, P_VERTEX = 2 };
+/* At most 2^20 pairs per stream: a segment that would need pair 2^20 ends
+ * absorbed (free flight) or blocked (shadow).  Valid scenes never come near
+ * it. */
+#define MAX_PAIRS ((int64_t)1 << 20)
 typedef struct { uint32_t key[2]; uint32_t ctr[3]; int64_t block; uint32_t words[4]; } ustream;
 
 static void us_init(ustream* u, uint64_t seed, uint32_t ray, uint32_t sample, uint32_t bounce, uint32_t purpose) {
@@ -411,7 +416,7 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
     for (int a = 0; a < 3; ++a) x[a] = P->center[a] + P->radius * po[a];
     if (P->jitter) {
         ustream uj;
-        us_init(&uj, P->seed, k, s, 0, P_JITTER);
+        us_init(&uj, P->seed, k, s, 0, P_FLIGHT);
         double u0 = us_get(&uj, 0), u1 = us_get(&uj, 1);
         double rho = 2.0 * P->radius / sqrt((double)P->M) * sqrt(u0);
         double ang = 2.0 * PI * u1;
@@ -437,14 +442,15 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
         tfsample te = {0, 0.0, 0.0, {0.0, 0.0, 0.0}};
         if (hit && sigbar > 0.0) {
             /* delta tracking: tentative collisions at rate sigbar; the n-th
-             * uses stream positions 2n (distance) and 2n+1 (acceptance) */
+             * uses pair n (n+1 on the first segment, after the jitter pair):
+             * distance, then acceptance */
             ustream uf;
             us_init(&uf, P->seed, k, s, (uint32_t)b, P_FLIGHT);
+            int64_t first = b == 0 ? 1 : 0;
             double t = tn;
-            int64_t step = 0;
-            for (;; ++step) {
-                if (step == MAX_STEPS) return; /* step cap: absorbed */
-                double ud = us_get(&uf, 2 * step), ua = us_get(&uf, 2 * step + 1);
+            for (int64_t pair = first;; ++pair) {
+                if (pair == MAX_PAIRS) return; /* cap reached: absorbed */
+                double ud = us_get(&uf, 2 * pair), ua = us_get(&uf, 2 * pair + 1);
                 t -= log(1.0 - ud) / sigbar;
                 if (t >= tf) break;
                 tr->stats[0] += 1.0;
@@ -519,12 +525,10 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
                 tr->sh_scale = 0.0;
             }
             if (sigbar > 0.0) {
-                ustream us;
-                us_init(&us, P->seed, k, s, (uint32_t)b, P_SHADOW);
                 double t = 0.0;
-                for (int64_t step = 0;; ++step) {
-                    if (step == MAX_STEPS) { Tr = 0.0; break; } /* step cap: blocked */
-                    t -= log(1.0 - us_get(&us, step)) / sigbar;
+                for (int64_t pair = 2;; ++pair) {
+                    if (pair == MAX_PAIRS) { Tr = 0.0; break; } /* cap reached: blocked */
+                    t -= log(1.0 - us_get(&uv, 2 * pair)) / sigbar;
                     if (t >= tend) break;
                     tr->stats[1] += 1.0;
                     double z[3];

@@ -32,7 +32,22 @@ int hip_fail(hipError_t e, const char* where) {
 
 bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
-constexpr size_t kWorkspaceBytes = 256;
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes of the volume's 4^3-brick copy (dimensions padded to multiples of 4).
+size_t brick4_bytes(const lf_volume* v) {
+    const size_t esz = v->type == LF_VOX_U8 ? 1 : (v->type == LF_VOX_U16 ? 2 : 4);
+    return align256(esz * 64 * (size_t)((v->nx + 3) / 4) * (size_t)((v->ny + 3) / 4) * (size_t)((v->nz + 3) / 4));
+}
+
+// lf_generate workspace: majorant (offset 0), 8 tile counters (offset 64),
+// spatial order of the generated origin rows (offset 256), spatial order of
+// the directions, then the brick copy of the volume.
+size_t gen_order_bytes(const lf_gen_params* p) {
+    const long long re = p->row_end <= 0 ? p->M : p->row_end;
+    const size_t rows = (size_t)(re - p->row_begin);
+    return 256 + align256(4 * rows) + align256(4 * (size_t)p->N);
+}
 
 int check_params(const lf_gen_params* p, bool need_rays) {
     if (!p) return fail(LF_E_ARG, "params is NULL");
@@ -58,7 +73,8 @@ int check_volume(const lf_volume* v) {
     if (!v->data) return fail(LF_E_ARG, "volume data is NULL");
     if (v->type < LF_VOX_U8 || v->type > LF_VOX_F32) return fail(LF_E_ARG, "unknown voxel type %d", v->type);
     if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(LF_E_ARG, "volume dimensions must be >= 2");
-    if ((unsigned long long)v->nx * v->ny * v->nz >= (1ull << 32)) return fail(LF_E_RANGE, "volume too large");
+    if (64ull * ((v->nx + 3) / 4) * ((v->ny + 3) / 4) * ((v->nz + 3) / 4) >= (1ull << 32))
+        return fail(LF_E_RANGE, "volume too large");
     const uintptr_t esz = v->type == LF_VOX_U8 ? 1 : (v->type == LF_VOX_U16 ? 2 : 4);
     if ((uintptr_t)v->data % esz) return fail(LF_E_ARG, "volume data is not aligned to its voxel size");
     if (v->brick != 0 && v->brick != 8) return fail(LF_E_UNSUPPORTED, "brick must be 0 or 8");
@@ -104,11 +120,11 @@ int check_light(const lf_light* l) {
 void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, const lf_medium* s,
                 const lf_light* l, const lf_gen_params* p) {
     std::memset(&T, 0, sizeof(T));
-    T.vol = v->data;
+    T.vol = v->data;  // replaced by the workspace's 4^3-brick copy
     T.nx = v->nx;
     T.ny = v->ny;
-    T.brick_row = 512 * (v->nx / 8);
-    T.brick_slab = 512 * (v->nx / 8) * (v->ny / 8);
+    T.brick_row = 64 * ((v->nx + 3) / 4);
+    T.brick_slab = 64 * ((v->nx + 3) / 4) * ((v->ny + 3) / 4);
     const int n[3] = {v->nx, v->ny, v->nz};
     for (int a = 0; a < 3; ++a) {
         const double ext = (double)v->box_max[a] - (double)v->box_min[a];
@@ -165,12 +181,11 @@ void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, cons
     T.stats = (unsigned long long*)p->stats;
 }
 
-int check_workspace(void* ws, size_t* ws_bytes) {
+int check_workspace(void* ws, size_t* ws_bytes, size_t need) {
     if (!ws_bytes) return fail(LF_E_ARG, "ws_bytes is NULL");
     if (!ws) return 1;  // size query
-    if (*ws_bytes < kWorkspaceBytes)
-        return fail(LF_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", *ws_bytes,
-                    kWorkspaceBytes);
+    if (*ws_bytes < need)
+        return fail(LF_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", *ws_bytes, need);
     if ((uintptr_t)ws % 16) return fail(LF_E_WORKSPACE, "workspace must be 16-byte aligned");
     return LF_OK;
 }
@@ -213,9 +228,10 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     }
     if (dtype < LF_F32 || dtype > LF_BF16) return fail(LF_E_ARG, "unknown light-field dtype %d", dtype);
     if (!lf_out) return fail(LF_E_ARG, "lf_out is NULL");
-    r = check_workspace(ws, ws_bytes);
+    const size_t need = gen_order_bytes(params) + brick4_bytes(vol);
+    r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
-        *ws_bytes = kWorkspaceBytes;
+        *ws_bytes = need;
         return LF_OK;
     }
     if (r) return r;
@@ -223,14 +239,25 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     pack_trace(T, vol, eval, sample, light, params);
     T.out = lf_out;
     T.dtype = dtype;
-    float* sig = (float*)ws;
+    char* w = (char*)ws;
+    float* sig = (float*)w;
+    unsigned int* ctr = (unsigned int*)(w + 64);
+    int32_t* perm_o = (int32_t*)(w + 256);
+    int32_t* perm_d = (int32_t*)(w + 256 + align256(4 * (size_t)(T.row_end - T.row_begin)));
     T.sigbar = sig;
+    T.tile_ctr = ctr;
+    T.perm_o = perm_o;
+    T.perm_d = perm_d;
+    T.vol = w + gen_order_bytes(params);
     const lf_medium* sm = sample ? sample : eval;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = lp::launch_majorant(sm->lut, sm->lut_size, sm->density_scale, params->majorant, sig, s);
-    if (e != hipSuccess) return hip_fail(e, "lf_generate (majorant)");
+    hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
+    if (e == hipSuccess)
+        e = lp::launch_wave_setup(T, sm->lut, sm->lut_size, sm->density_scale, params->majorant, sig, ctr, perm_o,
+                                  perm_d, s);
+    if (e != hipSuccess) return hip_fail(e, "lf_generate (set-up)");
     const int mode = (sample && sample != eval) ? lp::kFrozen : lp::kFwd;
-    e = lp::launch_generate(T, vol->type, vol->brick == 8, mode, s);
+    e = lp::launch_generate_wave(T, vol->type, mode, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate");
     return LF_OK;
 }
@@ -244,9 +271,10 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
         (r = check_params(params, true)))
         return r;
     if (!d_lf || !d_lut || !d_scale) return fail(LF_E_ARG, "d_lf, d_lut and d_scale must be non-NULL");
-    r = check_workspace(ws, ws_bytes);
+    const size_t need = 256 + brick4_bytes(vol);  // majorant, then the brick copy
+    r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
-        *ws_bytes = kWorkspaceBytes;
+        *ws_bytes = need;
         return LF_OK;
     }
     if (r) return r;
@@ -258,12 +286,14 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     T.stats = nullptr;
     float* sig = (float*)ws;
     T.sigbar = sig;
+    T.vol = (char*)ws + 256;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = lp::launch_zero(d_lut, 4ll * medium->lut_size, s);
+    hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
+    if (e == hipSuccess) e = lp::launch_zero(d_lut, 4ll * medium->lut_size, s);
     if (e == hipSuccess) e = lp::launch_zero(d_scale, 1, s);
     if (e == hipSuccess)
         e = lp::launch_majorant(medium->lut, medium->lut_size, medium->density_scale, params->majorant, sig, s);
-    if (e == hipSuccess) e = lp::launch_generate(T, vol->type, vol->brick == 8, lp::kGrad, s);
+    if (e == hipSuccess) e = lp::launch_backward(T, vol->type, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate_backward");
     return LF_OK;
 }

@@ -1,13 +1,13 @@
-// generate.hip -- light-field generation (Sec. 2, Fig. 1) and its adjoint.
+// generate.hip -- adjoint of light-field generation (path replay), plus the
+// small majorant and zero-fill kernels.
 //
 // Work decomposition: rays are grouped in 8 x 8 tiles (8 origins i x 8
 // directions j) and every wave64 takes whole tiles in a grid-stride loop, one
-// ray per lane.  All spp samples of a ray run in order in its lane, so the
-// texel is a deterministic FP32 sum, written once (12 B FP32 or 6 B
-// FP16/BF16 per texel).  The transfer function lives in LDS; the volume is
-// read with plain loads (it stays in L2 / the Infinity Cache for the 8-32 MiB
-// volumes).  The adjoint kernel keeps a per-workgroup LDS copy of dLUT and
-// flushes it with one atomic per entry at the end.
+// ray per lane; each sample is traced twice (its total radiance, then the
+// score replay).  Rays whose adjoint is zero are skipped, which removes most
+// of the work when the adjoint comes from a few views.  The transfer
+// function lives in LDS; the kernel keeps a per-workgroup LDS copy of dLUT
+// and flushes it with one atomic per entry at the end.
 #include <hip/hip_fp16.h>
 
 #include "internal.hpp"
@@ -32,43 +32,7 @@ __global__ void zero_kernel(float* p, long long n) {
     if (i < n) p[i] = 0.0f;
 }
 
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ void store_texel(const TraceParams& P, uint64_t k, f3 v) {
-    if (P.dtype == 0) {
-        float* o = (float*)P.out + 3 * k;
-        o[0] = v.x;
-        o[1] = v.y;
-        o[2] = v.z;
-    } else if (P.dtype == 1) {
-        __half* o = (__half*)P.out + 3 * k;
-        o[0] = __float2half_rn(v.x);
-        o[1] = __float2half_rn(v.y);
-        o[2] = __float2half_rn(v.z);
-    } else {
-        uint16_t* o = (uint16_t*)P.out + 3 * k;
-        o[0] = bf16_rne(v.x);
-        o[1] = bf16_rne(v.y);
-        o[2] = bf16_rne(v.z);
-    }
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ float wave_sumf(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-template <int VT, int BR, int MODE>
+template <int VT, int MODE>
 __global__ __launch_bounds__(256) void gen_kernel(TraceParams P) {
     extern __shared__ float4 smem[];
     float4* lut_e = smem;
@@ -120,12 +84,12 @@ __global__ __launch_bounds__(256) void gen_kernel(TraceParams P) {
             const f3 dir = normalize(pd - po);
             for (int s = 0; s < P.spp; ++s) {
                 if constexpr (MODE == kGrad) {
-                    const f3 lt = trace_sample<VT, BR, kFwd>(P, lut_e, lut_s, sigbar, inv_sigbar, k, po, dir,
+                    const f3 lt = trace_sample<VT, kFwd>(P, lut_e, lut_s, sigbar, inv_sigbar, k, po, dir,
                                                              (uint32_t)s, cnt, acc, adj, G);
-                    trace_sample<VT, BR, kGrad>(P, lut_e, lut_s, sigbar, inv_sigbar, k, po, dir, (uint32_t)s, cnt,
+                    trace_sample<VT, kGrad>(P, lut_e, lut_s, sigbar, inv_sigbar, k, po, dir, (uint32_t)s, cnt,
                                                 lt, adj, G);
                 } else {
-                    acc = acc + trace_sample<VT, BR, MODE>(P, lut_e, lut_s, sigbar, inv_sigbar, k, po, dir,
+                    acc = acc + trace_sample<VT, MODE>(P, lut_e, lut_s, sigbar, inv_sigbar, k, po, dir,
                                                            (uint32_t)s, cnt, acc, adj, G);
                 }
             }
@@ -169,42 +133,67 @@ hipError_t launch_zero(float* p, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int VT, int BR, int MODE>
-static hipError_t launch_gen_t(const TraceParams& P, hipStream_t s) {
+template <int VT>
+static hipError_t launch_bwd_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
     const long long ntiles = ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
     if (ntiles <= 0) return hipSuccess;
-    // 4 tiles (waves) per workgroup; the adjoint runs as a persistent grid so
-    // that only a few thousand workgroups flush their LDS gradients.
-    const long long cap = MODE == kGrad ? 2048 : 16384;
+    // 4 tiles (waves) per workgroup as a persistent grid, so that only a few
+    // thousand workgroups flush their LDS gradients.
     long long blocks = (ntiles + 3) / 4;
-    if (blocks > cap) blocks = cap;
-    const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
-                       (MODE == kGrad ? sizeof(float) * (4 * (size_t)P.lut_n + 1) : 0);
-    gen_kernel<VT, BR, MODE><<<(unsigned)blocks, 256, lds, s>>>(P);
+    if (blocks > 2048) blocks = 2048;
+    const size_t lds = sizeof(float4) * (size_t)P.lut_n + sizeof(float) * (4 * (size_t)P.lut_n + 1);
+    gen_kernel<VT, kGrad><<<(unsigned)blocks, 256, lds, s>>>(P);
     return hipGetLastError();
 }
 
-template <int VT, int BR>
-static hipError_t launch_gen_mode(const TraceParams& P, int mode, hipStream_t s) {
-    switch (mode) {
-        case kFwd: return launch_gen_t<VT, BR, kFwd>(P, s);
-        case kFrozen: return launch_gen_t<VT, BR, kFrozen>(P, s);
-        default: return launch_gen_t<VT, BR, kGrad>(P, s);
-    }
-}
-
-template <int VT>
-static hipError_t launch_gen_brick(const TraceParams& P, int brick, int mode, hipStream_t s) {
-    return brick ? launch_gen_mode<VT, 1>(P, mode, s) : launch_gen_mode<VT, 0>(P, mode, s);
-}
-
-hipError_t launch_generate(const TraceParams& P, int vtype, int brick, int mode, hipStream_t s) {
+hipError_t launch_backward(const TraceParams& P, int vtype, hipStream_t s) {
     switch (vtype) {
-        case 0: return launch_gen_brick<0>(P, brick, mode, s);
-        case 1: return launch_gen_brick<1>(P, brick, mode, s);
-        default: return launch_gen_brick<2>(P, brick, mode, s);
+        case 0: return launch_bwd_t<0>(P, s);
+        case 1: return launch_bwd_t<1>(P, s);
+        default: return launch_bwd_t<2>(P, s);
     }
+}
+
+// Copy of the input volume (x-fastest, or 8^3 bricks) into 4^3 bricks; the
+// padding beyond nx, ny, nz is never read (fetch coordinates are clamped).
+template <typename T>
+__global__ void brick4_kernel(const T* src, int layout, int nx, int ny, int nz, int nbx, int nby, long long total,
+                              T* dst) {
+    const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= total) return;
+    const long long bk = d >> 6;
+    const int w = (int)(d & 63);
+    const int bx = (int)(bk % nbx), by = (int)((bk / nbx) % nby), bz = (int)(bk / ((long long)nbx * nby));
+    const int x = bx * 4 + (w & 3), y = by * 4 + ((w >> 2) & 3), z = bz * 4 + (w >> 4);
+    T v = T(0);
+    if (x < nx && y < ny && z < nz) {
+        long long si;
+        if (layout == 8) {
+            const long long b8 = (x >> 3) + (long long)(nx >> 3) * ((y >> 3) + (long long)(ny >> 3) * (z >> 3));
+            si = b8 * 512 + (x & 7) + 8 * ((y & 7) + 8 * (z & 7));
+        } else {
+            si = x + (long long)nx * (y + (long long)ny * z);
+        }
+        v = src[si];
+    }
+    dst[d] = v;
+}
+
+hipError_t launch_brick4(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst, hipStream_t s) {
+    const int nbx = (nx + 3) / 4, nby = (ny + 3) / 4, nbz = (nz + 3) / 4;
+    const long long total = 64ll * nbx * nby * nbz;
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    if (vtype == 0)
+        brick4_kernel<uint8_t><<<blocks, 256, 0, s>>>((const uint8_t*)src, layout, nx, ny, nz, nbx, nby, total,
+                                                       (uint8_t*)dst);
+    else if (vtype == 1)
+        brick4_kernel<uint16_t><<<blocks, 256, 0, s>>>((const uint16_t*)src, layout, nx, ny, nz, nbx, nby, total,
+                                                        (uint16_t*)dst);
+    else
+        brick4_kernel<float><<<blocks, 256, 0, s>>>((const float*)src, layout, nx, ny, nz, nbx, nby, total,
+                                                     (float*)dst);
+    return hipGetLastError();
 }
 
 }  // namespace lp

@@ -11,8 +11,11 @@
 //     towards the light with ratio-tracking transmittance, Henyey-Greenstein
 //     direction for the next segment; escape: constant environment.
 // Random numbers: Philox4x32-10 keyed by the seed, counter (ray, sample,
-// bounce << 8 | purpose, block); one block feeds two tentative collisions or
-// four shadow steps.
+// bounce << 8 | purpose, block); a block holds two word pairs.  Purpose 1
+// ("flight" of segment b): pair 0 of segment 0 jitters the origin, then one
+// pair per tentative collision (distance, acceptance).  Purpose 2 ("vertex"
+// b): pair 0 samples the light, pair 1 the phase function, then one pair per
+// shadow step (first word: distance).
 //
 // The same routine runs in three modes:
 //   kFwd     plain estimator;
@@ -23,23 +26,25 @@
 //            LDS accumulators (dLUT, dscale).
 #pragma once
 
+#include <hip/hip_fp16.h>
+
 #include "sf_device.hpp"
 
 namespace lp {
 
 enum { kFwd = 0, kFrozen = 1, kGrad = 2 };
-enum { kPurJitter = 0, kPurFlight = 1, kPurVertex = 2, kPurShadow = 3 };
-// At most 2^20 tentative collisions per segment (free flight or shadow ray).
-// Valid scenes stay orders of magnitude below; a segment that reaches it ends
-// absorbed (free flight) or fully blocked (shadow), so no lane can spin.
-constexpr uint32_t kMaxFlightBlocks = 1u << 19;  // 2 collisions per block
-constexpr uint32_t kMaxShadowBlocks = 1u << 18;  // 4 steps per block
+enum { kPurFlight = 1, kPurVertex = 2 };
+// At most 2^20 word pairs (2^19 blocks) per stream.  Valid scenes stay orders
+// of magnitude below; a segment that reaches it ends absorbed (free flight)
+// or fully blocked (shadow), so no lane can spin.
+constexpr uint32_t kMaxBlocks = 1u << 19;
 
 struct TraceParams {
-    // volume
+    // volume: the library's 4^3-brick copy (bricks x-fastest, voxels
+    // x-fastest inside a brick; 4 x 4 x 4 u16 voxels fill one 128-byte line)
     const void* vol;
     int32_t nx, ny;
-    int32_t brick_row, brick_slab;   // bricked: 512 * nbx, 512 * nbx * nby
+    int32_t brick_row, brick_slab;   // 64 * bricks per row, 64 * bricks per slab
     float ga[3], gb[3];              // grid coordinate = x * ga + gb
     float gmax[3];                   // n - 1
     int32_t imax[3];                 // n - 2
@@ -73,6 +78,11 @@ struct TraceParams {
     const float* d_lf;
     float* d_lut;
     float* d_scale;
+    // persistent forward kernel: spatial orders of the origin rows and the
+    // directions, and the per-XCD tile counters (workspace)
+    const int32_t* perm_o;
+    const int32_t* perm_d;
+    unsigned int* tile_ctr;
 };
 
 struct Counters {
@@ -89,11 +99,10 @@ __device__ __forceinline__ float vox(const void* v, uint32_t idx) {
     else return ((const float*)v)[idx];
 }
 
-template <int BR>
-__device__ __forceinline__ uint32_t ax_x(int x) { return BR ? (uint32_t)((x >> 3) * 512 + (x & 7)) : (uint32_t)x; }
-
-// Trilinear raw value at world point y (edge-clamped grid coordinates).
-template <int VT, int BR>
+// Trilinear raw value at world point y (edge-clamped grid coordinates) from
+// the 4^3-brick copy: the 2 x 2 x 2 footprint lies in one 128-byte line for
+// (3/4)^3 of the points and in 1.95 lines on average (x-fastest rows: 4).
+template <int VT>
 __device__ __forceinline__ float sample_volume(const TraceParams& P, f3 y) {
     const float gx = fminf(fmaxf(fmaf(y.x, P.ga[0], P.gb[0]), 0.0f), P.gmax[0]);
     const float gy = fminf(fmaxf(fmaf(y.y, P.ga[1], P.gb[1]), 0.0f), P.gmax[1]);
@@ -102,22 +111,12 @@ __device__ __forceinline__ float sample_volume(const TraceParams& P, f3 y) {
     const int iy = min((int)gy, P.imax[1]);
     const int iz = min((int)gz, P.imax[2]);
     const float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
-    uint32_t x0, x1, y0, y1, z0, z1;
-    if constexpr (BR) {
-        x0 = ax_x<1>(ix);
-        x1 = ax_x<1>(ix + 1);
-        y0 = (uint32_t)((iy >> 3) * P.brick_row + (iy & 7) * 8);
-        y1 = (uint32_t)(((iy + 1) >> 3) * P.brick_row + ((iy + 1) & 7) * 8);
-        z0 = (uint32_t)((iz >> 3) * P.brick_slab + (iz & 7) * 64);
-        z1 = (uint32_t)(((iz + 1) >> 3) * P.brick_slab + ((iz + 1) & 7) * 64);
-    } else {
-        x0 = (uint32_t)ix;
-        x1 = x0 + 1;
-        y0 = (uint32_t)iy * (uint32_t)P.nx;
-        y1 = y0 + (uint32_t)P.nx;
-        z0 = (uint32_t)iz * (uint32_t)P.nx * (uint32_t)P.ny;
-        z1 = z0 + (uint32_t)P.nx * (uint32_t)P.ny;
-    }
+    const uint32_t x0 = (uint32_t)((ix >> 2) * 64 + (ix & 3));
+    const uint32_t x1 = (uint32_t)(((ix + 1) >> 2) * 64 + ((ix + 1) & 3));
+    const uint32_t y0 = (uint32_t)((iy >> 2) * P.brick_row + (iy & 3) * 4);
+    const uint32_t y1 = (uint32_t)(((iy + 1) >> 2) * P.brick_row + ((iy + 1) & 3) * 4);
+    const uint32_t z0 = (uint32_t)((iz >> 2) * P.brick_slab + (iz & 3) * 16);
+    const uint32_t z1 = (uint32_t)(((iz + 1) >> 2) * P.brick_slab + ((iz + 1) & 3) * 16);
     const float v000 = vox<VT>(P.vol, x0 + y0 + z0), v100 = vox<VT>(P.vol, x1 + y0 + z0);
     const float v010 = vox<VT>(P.vol, x0 + y1 + z0), v110 = vox<VT>(P.vol, x1 + y1 + z0);
     const float v001 = vox<VT>(P.vol, x0 + y0 + z1), v101 = vox<VT>(P.vol, x1 + y0 + z1);
@@ -247,14 +246,14 @@ struct GradAcc {
 // `ltot` is this sample's radiance from a forward replay and `adj` the
 // adjoint of the texel divided by spp.
 // ---------------------------------------------------------------------------
-template <int VT, int BR, int MODE>
+template <int VT, int MODE>
 __device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const float4* lut_s, float sigbar,
                            float inv_sigbar, uint32_t k, f3 po, f3 dir, uint32_t s, Counters& cnt, f3 ltot,
                            f3 adj, GradAcc& G) {
     const uint32_t K0 = P.key0, K1 = P.key1;
     f3 x = mk3(P.O[0], P.O[1], P.O[2]) + po * P.R;
     if (P.jitter) {
-        const u4 r = philox(k, s, kPurJitter, 0, K0, K1);
+        const u4 r = philox(k, s, kPurFlight, 0, K0, K1);
         const float rho = P.jit_rad * sqrtf(u01(r.x));
         float sa, ca;
         sincospif(2.0f * u01(r.y), &sa, &ca);
@@ -282,10 +281,11 @@ __device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const floa
             const uint32_t c2 = ((uint32_t)b << 8) | kPurFlight;
             float t = tn;
             bool done = false;
-            for (uint32_t blk = 0; blk < kMaxFlightBlocks; ++blk) {
+            for (uint32_t blk = 0; blk < kMaxBlocks; ++blk) {
                 const u4 r = philox(k, s, c2, blk, K0, K1);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
+                    if (b == 0 && blk == 0 && h == 0) continue;  // jitter pair
                     const uint32_t ud = h ? r.z : r.x, ua = h ? r.w : r.y;
                     t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
                     if (t >= tf) {
@@ -294,7 +294,7 @@ __device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const floa
                     }
                     cnt.tent++;
                     y = fma3(dir, t, x);
-                    te = classify<MODE>(P, lut_e, lut_s, sample_volume<VT, BR>(P, y));
+                    te = classify<MODE>(P, lut_e, lut_s, sample_volume<VT>(P, y));
                     const float sig_e = P.scale_e * te.a;
                     const float sig_s = MODE == kFrozen ? P.scale_s * te.a_s : sig_e;
                     if (u01(ua) * sigbar < sig_s) {
@@ -361,21 +361,21 @@ __device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const floa
             }
             float Tr = 1.0f;
             if (sigbar > 0.0f) {
-                const uint32_t c2 = ((uint32_t)b << 8) | kPurShadow;
+                const uint32_t c2 = ((uint32_t)b << 8) | kPurVertex;
                 float t = 0.0f;
                 bool done = false;
-                for (uint32_t blk = 0; blk < kMaxShadowBlocks; ++blk) {
+                for (uint32_t blk = 1; blk < kMaxBlocks; ++blk) {
                     const u4 r = philox(k, s, c2, blk, K0, K1);
 #pragma unroll
-                    for (int h = 0; h < 4; ++h) {
-                        const uint32_t ud = h == 0 ? r.x : (h == 1 ? r.y : (h == 2 ? r.z : r.w));
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t ud = h ? r.z : r.x;
                         t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
                         if (t >= tend) {
                             done = true;
                             break;
                         }
                         cnt.shadow++;
-                        const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT, BR>(P, fma3(om, t, x)));
+                        const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT>(P, fma3(om, t, x)));
                         Tr *= 1.0f - P.scale_e * ts.a * inv_sigbar;
                     }
                     if (done) break;
@@ -389,20 +389,20 @@ __device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const floa
                 // NEE term only: replay the shadow steps now that Tr is known
                 const float rc = dot(adj, C);
                 if (rc != 0.0f && sigbar > 0.0f) {
-                    const uint32_t c2 = ((uint32_t)b << 8) | kPurShadow;
+                    const uint32_t c2 = ((uint32_t)b << 8) | kPurVertex;
                     float t = 0.0f;
-                    for (uint32_t blk = 0; blk < kMaxShadowBlocks; ++blk) {
+                    for (uint32_t blk = 1; blk < kMaxBlocks; ++blk) {
                         const u4 r = philox(k, s, c2, blk, K0, K1);
                         bool done = false;
 #pragma unroll
-                        for (int h = 0; h < 4; ++h) {
-                            const uint32_t ud = h == 0 ? r.x : (h == 1 ? r.y : (h == 2 ? r.z : r.w));
+                        for (int h = 0; h < 2; ++h) {
+                            const uint32_t ud = h ? r.z : r.x;
                             t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
                             if (t >= tend) {
                                 done = true;
                                 break;
                             }
-                            const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT, BR>(P, fma3(om, t, x)));
+                            const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT>(P, fma3(om, t, x)));
                             G.sigma(ts, P.scale_e, -rc / (sigbar - P.scale_e * ts.a));
                         }
                         if (done) break;
@@ -421,6 +421,45 @@ __device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const floa
         dir = t1 * (st * cp) + t2 * (st * sp) + dir * mu;
     }
     return L;
+}
+
+// ---------------------------------------------------------------------------
+// Texel store (FP32 / FP16 / BF16, round to nearest even) and wave sums
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ void store_texel(const TraceParams& P, uint64_t k, f3 v) {
+    if (P.dtype == 0) {
+        float* o = (float*)P.out + 3 * k;
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+    } else if (P.dtype == 1) {
+        __half* o = (__half*)P.out + 3 * k;
+        o[0] = __float2half_rn(v.x);
+        o[1] = __float2half_rn(v.y);
+        o[2] = __float2half_rn(v.z);
+    } else {
+        uint16_t* o = (uint16_t*)P.out + 3 * k;
+        o[0] = bf16_rne(v.x);
+        o[1] = bf16_rne(v.y);
+        o[2] = bf16_rne(v.z);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 }  // namespace lp

@@ -1,0 +1,434 @@
+// wave.hip -- persistent light-field generation kernel (forward and frozen
+// sampling modes).
+//
+// Paths differ wildly in cost: a ray that misses the volume is done after
+// one clip, a ray through dense tissue scatters and casts shadow rays.  With
+// one ray per lane and all of a ray's samples in a loop, a wave64 runs as
+// long as its most expensive lane; measured lane utilisation was 17 %.  Here
+// every lane runs its own state machine
+//     IDLE -> START -> FLIGHT <-> VERTEX -> SHADOW -> FLIGHT ... -> IDLE
+// and every loop iteration advances all lanes by one Philox4x32-10 block:
+//   START   pair 0 jitters the origin, pair 1 is the first tentative collision;
+//   FLIGHT  two tentative collisions (delta tracking);
+//   VERTEX  light sample and phase-function words (NEE set-up);
+//   SHADOW  two ratio-tracking steps towards the light.
+// Both tentative points of a block are fetched before either is classified,
+// so a lane keeps 16 voxel loads in flight.  A lane whose sample ends starts
+// the next sample of its ray in the next iteration; a lane whose ray is done
+// takes the next ray of its wave's current 8 x 8 tile, and the wave takes a
+// new tile when the current one is used up (one atomic per tile).
+//
+// Ray order: origins and directions are each sorted into latitude bands of
+// ~5 sqrt(n) consecutive SF indices, by azimuth inside a band, so a tile's
+// 64 rays run between two small patches of S; tiles are taken in groups of 16
+// origin tiles sweeping the direction tiles, and the tile sequence is cut into
+// 8 contiguous parts, one per XCD (workgroups are dispatched round-robin over
+// the XCDs), so each XCD's L2 sees a narrow bundle of rays.  A part that runs
+// dry hands out tiles of the next parts.  Results do not depend on the order:
+// every random number is keyed by (ray, sample, bounce).
+#include "internal.hpp"
+
+namespace lp {
+
+enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4 };
+constexpr int kGroupTiles = 16;
+constexpr int kParts = 8;
+
+// Tile t of the row slab -> (origin tile, direction tile).
+__device__ __forceinline__ void tile_coords(long long t, int tiles_i, int tiles_j, int& ti, int& tj) {
+    const long long per_group = (long long)kGroupTiles * tiles_j;
+    const int gi = (int)(t / per_group);
+    const int gsz = min(kGroupTiles, tiles_i - gi * kGroupTiles);
+    const long long off = t - (long long)gi * per_group;
+    tj = (int)(off / gsz);
+    ti = gi * kGroupTiles + (int)(off - (long long)tj * gsz);
+}
+
+// Next tile for a wave whose home part is `home`; -1 when all are taken.
+__device__ __forceinline__ long long next_tile(unsigned int* ctr, long long ntiles, int home, unsigned& dry) {
+    const long long part = (ntiles + kParts - 1) / kParts;
+    for (int q = 0; q < kParts; ++q) {
+        const int p = (home + q) % kParts;
+        if (dry & (1u << p)) continue;
+        const long long lo = (long long)p * part;
+        const long long n = min(part, ntiles - lo);
+        if (n <= 0) {
+            dry |= 1u << p;
+            continue;
+        }
+        const unsigned got = atomicAdd(&ctr[p], 1u);
+        if ((long long)got < n) return lo + got;
+        dry |= 1u << p;
+    }
+    return -1;
+}
+
+template <int VT, int MODE>
+__global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
+    extern __shared__ float4 smem[];
+    float4* lut_e = smem;
+    float4* lut_s = smem + (MODE == kFrozen ? P.lut_n : 0);
+    for (int e = threadIdx.x; e < P.lut_n; e += blockDim.x) {
+        lut_e[e] = ((const float4*)P.lut_e)[e];
+        if constexpr (MODE == kFrozen) lut_s[e] = ((const float4*)P.lut_s)[e];
+    }
+    __syncthreads();
+
+    const float sigbar = *P.sigbar;
+    const float inv_sigbar = sigbar > 0.0f ? 1.0f / sigbar : 0.0f;
+    const uint32_t K0 = P.key0, K1 = P.key1;
+    const int lane = threadIdx.x & 63;
+    const int rows = P.row_end - P.row_begin;
+    const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
+    const long long ntiles = (long long)tiles_i * tiles_j;
+    const int home = blockIdx.x % kParts;
+    const float invM = 1.0f / (float)P.M, invN = 1.0f / (float)P.N;
+    const f3 O = mk3(P.O[0], P.O[1], P.O[2]);
+    const f3 env = mk3(P.env[0], P.env[1], P.env[2]);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    // wave-uniform queue cursor: rays [cur, end) of the current tile
+    long long cur = 0, end = 0;
+    unsigned dry = 0;
+    bool drained = false;
+
+    // lane state
+    int mode = kIdle;
+    uint32_t k = 0, blk = 0;
+    int s = 0, b = 0;
+    f3 po = mk3(0, 0, 0), d0 = po, acc = po, x = po, dir = po, T = po, L = po, om = po, C = po;
+    float W = 1.0f, t = 0.0f, tend = 0.0f, Tr = 1.0f, up0 = 0.0f, up1 = 0.0f;
+    Counters cnt = {0, 0, 0, 0};
+
+    for (;;) {
+        // ------------------------------------------------------------ refill
+        const uint64_t idle = __ballot(mode == kIdle);
+        if (idle) {
+            const int nidle = __popcll(idle);
+            const int rank = __popcll(idle & lt_mask);
+            long long avail = end - cur;
+            long long fresh = -1;
+            if (nidle > avail && !drained) {
+                long long tl = 0;
+                if (lane == 0) tl = next_tile(P.tile_ctr, ntiles, home, dry);
+                tl = __shfl(tl, 0, 64);
+                dry = __shfl(dry, 0, 64);
+                if (tl < 0) drained = true;
+                else fresh = tl * 64;
+            }
+            long long q = -1;
+            if (mode == kIdle) {
+                if (rank < avail) q = cur + rank;
+                else if (fresh >= 0) q = fresh + (rank - avail);
+            }
+            if (fresh >= 0) {
+                cur = fresh + (nidle - avail);
+                end = fresh + 64;
+            } else {
+                cur += min((long long)nidle, avail);
+            }
+            if (q >= 0) {
+                int ti, tj;
+                tile_coords(q >> 6, tiles_i, tiles_j, ti, tj);
+                const int oi = ti * 8 + (int)((q >> 3) & 7), dj = tj * 8 + (int)(q & 7);
+                if (oi < rows && dj < P.N) {
+                    const int i = P.perm_o[oi], j = P.perm_d[dj];
+                    k = (uint32_t)i * (uint32_t)P.N + (uint32_t)j;
+                    if (P.M == P.N && i == j) {
+                        store_texel(P, k, mk3(0.0f, 0.0f, 0.0f));  // no direction: texel 0
+                    } else {
+                        po = sf_point(P.M, i, invM);
+                        d0 = normalize(sf_point(P.N, j, invN) - po);
+                        acc = mk3(0.0f, 0.0f, 0.0f);
+                        s = 0;
+                        b = 0;
+                        blk = 0;
+                        mode = kStart;
+                    }
+                }
+            }
+        }
+        if (__ballot(mode != kIdle) == 0) {
+            if (drained && end <= cur) break;
+            continue;
+        }
+
+        // ------------------------------------------------------ one block
+        const bool vstream = mode == kVertex || mode == kShadow;
+        const u4 r = philox(k, (uint32_t)s, ((uint32_t)b << 8) | (vstream ? kPurVertex : kPurFlight), blk, K0, K1);
+        bool stepA = mode == kFlight || mode == kShadow;
+        bool stepB = stepA;
+        bool sample_done = false, after_shadow = false;
+
+        if (mode == kStart) {
+            cnt.samples++;
+            x = O + po * P.R;
+            if (P.jitter) {
+                const float rho = P.jit_rad * sqrtf(u01(r.x));
+                float sa, ca;
+                sincospif(2.0f * u01(r.y), &sa, &ca);
+                f3 t1, t2;
+                frame(po, t1, t2);
+                x = x + (t1 * (rho * ca) + t2 * (rho * sa));
+            }
+            dir = d0;
+            T = mk3(1.0f, 1.0f, 1.0f);
+            W = 1.0f;
+            L = mk3(0.0f, 0.0f, 0.0f);
+            float tn, tf;
+            if (clip_box(P, x, dir, tn, tf) && sigbar > 0.0f) {
+                t = tn;
+                tend = tf;
+                mode = kFlight;
+                stepB = true;  // pair 1 is the first tentative collision
+            } else {
+                L = L + T * env * W;
+                sample_done = true;
+            }
+        } else if (mode == kVertex) {
+            // next-event estimation set-up: light sample (pair 0), phase words (pair 1)
+            up0 = u01(r.z);
+            up1 = u01(r.w);
+            if (P.light_on) {
+                f3 Le;
+                float te = 0.0f;
+                if (P.light_kind == 0) {
+                    om = mk3(P.ldir[0], P.ldir[1], P.ldir[2]);
+                    Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]);
+                    float a0, a1;
+                    if (clip_box(P, x, om, a0, a1)) te = a1;
+                } else {
+                    const f3 yl = mk3(P.lcorner[0], P.lcorner[1], P.lcorner[2]) +
+                                  mk3(P.le1[0], P.le1[1], P.le1[2]) * u01(r.x) +
+                                  mk3(P.le2[0], P.le2[1], P.le2[2]) * u01(r.y);
+                    const f3 v = yl - x;
+                    const float dist = sqrtf(dot(v, v));
+                    om = v * (1.0f / dist);
+                    const float cl = fmaxf(0.0f, -dot(mk3(P.lnrm[0], P.lnrm[1], P.lnrm[2]), om));
+                    Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * (cl * P.larea / (dist * dist));
+                    float a0, a1;
+                    te = dist;
+                    if (clip_box(P, x, om, a0, a1)) te = fminf(te, a1);
+                    else te = 0.0f;
+                }
+                C = T * Le * (W * hg_phase(P.g, dot(dir, om)));
+                Tr = 1.0f;
+                if (sigbar > 0.0f) {
+                    t = 0.0f;
+                    tend = te;
+                    mode = kShadow;
+                    blk = 1;
+                } else {
+                    L = L + C;
+                    after_shadow = true;
+                }
+            } else {
+                after_shadow = true;
+            }
+        }
+
+        // -------------------------------------------- two tentative points
+        bool ev_end = false, ev_real = false;
+        f3 ynew = x;
+        TF te;
+        te.l0 = 0;
+        te.w = 0.0f;
+        te.a = te.a_s = 0.0f;
+        te.rgb = mk3(0.0f, 0.0f, 0.0f);
+        if (stepA || stepB) {
+            const f3 sd = mode == kShadow ? om : dir;
+            const float tA = fmaf(neg_log1m(u01(r.x)), inv_sigbar, t);
+            const float tB = fmaf(neg_log1m(u01(r.z)), inv_sigbar, stepA ? tA : t);
+            const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
+            const float rawA = sample_volume<VT>(P, yA);
+            const float rawB = sample_volume<VT>(P, yB);
+            bool more = true;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool use = h ? stepB : stepA;
+                if (!use || !more) continue;
+                const float th = h ? tB : tA;
+                if (th >= tend) {
+                    ev_end = true;
+                    more = false;
+                    continue;
+                }
+                const TF tf = classify<MODE>(P, lut_e, lut_s, h ? rawB : rawA);
+                const float sig_e = P.scale_e * tf.a;
+                t = th;
+                if (mode == kFlight) {
+                    cnt.tent++;
+                    const float sig_s = MODE == kFrozen ? P.scale_s * tf.a_s : sig_e;
+                    if (u01(h ? r.w : r.y) * sigbar < sig_s) {
+                        ev_real = true;
+                        more = false;
+                        ynew = h ? yB : yA;
+                        te = tf;
+                        if constexpr (MODE == kFrozen) W *= sig_e / sig_s;
+                    } else {
+                        if constexpr (MODE == kFrozen) W *= (sigbar - sig_e) / (sigbar - sig_s);
+                    }
+                } else {
+                    cnt.shadow++;
+                    Tr *= 1.0f - sig_e * inv_sigbar;
+                }
+            }
+            if (ev_end) {
+                if (mode == kFlight) {
+                    L = L + T * env * W;
+                    sample_done = true;
+                } else {
+                    L = L + C * Tr;
+                    after_shadow = true;
+                }
+            } else if (ev_real) {
+                cnt.real++;
+                x = ynew;
+                T = T * mk3(fminf(fmaxf(te.rgb.x, 0.0f), 1.0f), fminf(fmaxf(te.rgb.y, 0.0f), 1.0f),
+                            fminf(fmaxf(te.rgb.z, 0.0f), 1.0f));
+                if (T.x == 0.0f && T.y == 0.0f && T.z == 0.0f) {
+                    sample_done = true;
+                } else {
+                    mode = kVertex;
+                    blk = 0;
+                }
+            } else if (++blk >= kMaxBlocks) {
+                // stream exhausted: the segment ends absorbed / blocked
+                if (mode == kFlight) sample_done = true;
+                else after_shadow = true;
+            }
+        }
+
+        // ------------------------------------------------ scatter direction
+        if (after_shadow) {
+            if (b == P.maxb - 1) {
+                sample_done = true;
+            } else {
+                const float mu = hg_mu(P.g, up0);
+                const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+                float sp, cp;
+                sincospif(2.0f * up1, &sp, &cp);
+                f3 t1, t2;
+                frame(dir, t1, t2);
+                dir = t1 * (st * cp) + t2 * (st * sp) + dir * mu;
+                ++b;
+                float tn, tf;
+                if (clip_box(P, x, dir, tn, tf) && sigbar > 0.0f) {
+                    t = tn;
+                    tend = tf;
+                    mode = kFlight;
+                    blk = 0;
+                } else {
+                    L = L + T * env * W;
+                    sample_done = true;
+                }
+            }
+        }
+
+        // ------------------------------------------------------ sample end
+        if (sample_done) {
+            acc = acc + L;
+            if (++s == P.spp) {
+                const float fs = (float)P.spp;
+                store_texel(P, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
+                mode = kIdle;
+            } else {
+                mode = kStart;
+                b = 0;
+                blk = 0;
+            }
+        }
+    }
+
+    if (P.stats) {
+        const uint32_t a = wave_sum(cnt.tent), c = wave_sum(cnt.shadow), e = wave_sum(cnt.real),
+                       f = wave_sum(cnt.samples);
+        if (lane == 0) {
+            atomicAdd(&P.stats[0], (unsigned long long)a);
+            atomicAdd(&P.stats[1], (unsigned long long)c);
+            atomicAdd(&P.stats[2], (unsigned long long)e);
+            atomicAdd(&P.stats[3], (unsigned long long)f);
+        }
+    }
+}
+
+// Spatial order of count consecutive SF indices base..base+count-1 of a set
+// of n points: bands of B indices, each sorted by azimuth (rank counting).
+__global__ void sf_order_kernel(int base, int count, int band, int32_t* out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const int lo = (e / band) * band;
+    const int hi = min(count, lo + band);
+    const float fe = sf_frac(base + e);
+    int rank = 0;
+    for (int f = lo; f < hi; ++f) {
+        const float ff = sf_frac(base + f);
+        rank += ff < fe || (ff == fe && f < e);
+    }
+    out[lo + rank] = base + e;
+}
+
+__global__ void wave_setup_kernel(const float* lut, int n, float scale, float given, float* sigbar,
+                                  unsigned int* ctr) {
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (int e = threadIdx.x; e < n; e += 256) m = fmaxf(m, lut[4 * e + 3]);
+    red[threadIdx.x] = m;
+    if (threadIdx.x < kParts) ctr[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sigbar[0] = given > 0.0f ? given : 1.25f * scale * red[0];
+}
+
+static int band_size(int n) {
+    int b = (int)(5.0 * std::sqrt((double)n));
+    b &= ~7;
+    return b < 8 ? 8 : b;
+}
+
+hipError_t launch_wave_setup(const TraceParams& P, const float* sample_lut, int lut_n, float sample_scale,
+                             float given, float* sigbar, unsigned int* ctr, int32_t* perm_o, int32_t* perm_d,
+                             hipStream_t s) {
+    wave_setup_kernel<<<1, 256, 0, s>>>(sample_lut, lut_n, sample_scale, given, sigbar, ctr);
+    const int rows = P.row_end - P.row_begin;
+    if (rows > 0) sf_order_kernel<<<(rows + 255) / 256, 256, 0, s>>>(P.row_begin, rows, band_size(P.M), perm_o);
+    sf_order_kernel<<<(P.N + 255) / 256, 256, 0, s>>>(0, P.N, band_size(P.N), perm_d);
+    return hipGetLastError();
+}
+
+template <int VT, int MODE>
+static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
+    const long long rows = P.row_end - P.row_begin;
+    const long long ntiles = ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
+    if (ntiles <= 0) return hipSuccess;
+    const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE>, 256, lds);
+    if (e != hipSuccess) return e;
+    long long blocks = (long long)cus * (per_cu > 0 ? per_cu : 1);
+    const long long need = (ntiles + 3) / 4;  // at least one tile per wave
+    if (blocks > need) blocks = need;
+    gen_wave_kernel<VT, MODE><<<(unsigned)blocks, 256, lds, s>>>(P);
+    return hipGetLastError();
+}
+
+template <int VT>
+static hipError_t launch_wave_mode(const TraceParams& P, int mode, hipStream_t s) {
+    return mode == kFrozen ? launch_wave_t<VT, kFrozen>(P, s) : launch_wave_t<VT, kFwd>(P, s);
+}
+
+hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipStream_t s) {
+    switch (vtype) {
+        case 0: return launch_wave_mode<0>(P, mode, s);
+        case 1: return launch_wave_mode<1>(P, mode, s);
+        default: return launch_wave_mode<2>(P, mode, s);
+    }
+}
+
+}  // namespace lp

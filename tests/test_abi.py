@@ -83,7 +83,9 @@ def err(lp):
 def test_workspace_size_query(lp):
     vol, med, light, prm = scene(lp)
     r, sz = call_generate(lp, vol, med, light, prm)
-    assert r == LF_OK and sz == 256
+    # majorant + counters, the spatial orders of 64 origins and 64 directions,
+    # then the 4^3-brick copy of the 16^3 u8 volume
+    assert r == LF_OK and sz == 256 + 256 + 256 + 4096
 
 
 @pytest.mark.parametrize("mutate,code,msg", [
