@@ -271,7 +271,11 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
         (r = check_params(params, true)))
         return r;
     if (!d_lf || !d_lut || !d_scale) return fail(LF_E_ARG, "d_lf, d_lut and d_scale must be non-NULL");
-    const size_t need = 256 + brick4_bytes(vol);  // majorant, then the brick copy
+    // majorant, counters, spatial orders, list of rays with a nonzero adjoint,
+    // then the brick copy of the volume
+    const long long re = params->row_end <= 0 ? params->M : params->row_end;
+    const size_t list_bytes = align256(4 * (size_t)(re - params->row_begin) * (size_t)params->N);
+    const size_t need = gen_order_bytes(params) + list_bytes + brick4_bytes(vol);
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -284,16 +288,27 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     T.d_lut = d_lut;
     T.d_scale = d_scale;
     T.stats = nullptr;
-    float* sig = (float*)ws;
+    char* w = (char*)ws;
+    float* sig = (float*)w;
+    unsigned int* ctr = (unsigned int*)(w + 64);
+    int32_t* perm_o = (int32_t*)(w + 256);
+    int32_t* perm_d = (int32_t*)(w + 256 + align256(4 * (size_t)(T.row_end - T.row_begin)));
     T.sigbar = sig;
-    T.vol = (char*)ws + 256;
+    T.tile_ctr = ctr;
+    T.ray_count = ctr + 8;
+    T.perm_o = perm_o;
+    T.perm_d = perm_d;
+    T.ray_list = (uint32_t*)(w + gen_order_bytes(params));
+    T.vol = w + gen_order_bytes(params) + list_bytes;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
     if (e == hipSuccess) e = lp::launch_zero(d_lut, 4ll * medium->lut_size, s);
     if (e == hipSuccess) e = lp::launch_zero(d_scale, 1, s);
     if (e == hipSuccess)
-        e = lp::launch_majorant(medium->lut, medium->lut_size, medium->density_scale, params->majorant, sig, s);
-    if (e == hipSuccess) e = lp::launch_backward(T, vol->type, s);
+        e = lp::launch_wave_setup(T, medium->lut, medium->lut_size, medium->density_scale, params->majorant, sig,
+                                  ctr, perm_o, perm_d, s);
+    if (e == hipSuccess) e = lp::launch_active_rays(T, s);
+    if (e == hipSuccess) e = lp::launch_generate_wave(T, vol->type, lp::kGrad, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate_backward");
     return LF_OK;
 }

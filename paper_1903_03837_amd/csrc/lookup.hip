@@ -7,8 +7,10 @@
 // view ray -> front/back hits on S (tangential rays discarded) -> O(1)
 // inverse SF mapping of each hit -> K nearest of the nine lattice
 // candidates -> tent weights -> K x K gathers (25 at K = 5) -> normalised
-// blend.  The adjoint mode scatters weight x d(img) into d(Lhat) with float
-// atomics.
+// blend.  The adjoint mode sorts each pixel's neighbour lists by index, so
+// the pixels of a wave, which share their neighbour sets, hold the same
+// texel in the same pair slot; equal texels are summed across the wave and
+// one float atomic per channel is issued per distinct texel.
 #include <hip/hip_fp16.h>
 
 #include "internal.hpp"
@@ -30,12 +32,142 @@ __device__ __forceinline__ f3 load_texel(const void* lf, uint64_t t) {
     }
 }
 
+// Sort (idx, w) pairs by index (static compare-exchange passes, registers
+// only).  In the adjoint this makes neighbouring pixels, which share their
+// neighbour sets, list the same texel in the same pair slot.
+template <int KMAX>
+__device__ __forceinline__ void sort_by_index(int* idx, float* w) {
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p)
+#pragma unroll
+        for (int a = (p & 1); a + 1 < KMAX; a += 2) {
+            const unsigned ia = (unsigned)idx[a], ib = (unsigned)idx[a + 1];  // -1 sorts last
+            if (ib < ia) {
+                const int ti = idx[a];
+                idx[a] = idx[a + 1];
+                idx[a + 1] = ti;
+                const float tw = w[a];
+                w[a] = w[a + 1];
+                w[a + 1] = tw;
+            }
+        }
+}
+
+// Wave-aggregated scatter-add of a 3-vector: lanes holding the same texel
+// are summed with cross-lane adds and one lane issues the three atomics.
+// Each pass retires every lane whose key equals the first pending lane's.
+__device__ __forceinline__ void wave_scatter_add(float* d_lf, bool pending, uint64_t key, f3 v) {
+    const int lane = threadIdx.x & 63;
+    uint64_t live = __ballot(pending);
+    while (live) {
+        const int leader = __ffsll((long long)live) - 1;
+        const uint64_t lk = __shfl(key, leader, 64);
+        const bool mine = pending && key == lk;
+        float a = mine ? v.x : 0.0f, b = mine ? v.y : 0.0f, c = mine ? v.z : 0.0f;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o, 64);
+            b += __shfl_xor(b, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if (lane == leader) {
+            float* dl = d_lf + 3 * lk;
+            atomicAdd(dl + 0, a);
+            atomicAdd(dl + 1, b);
+            atomicAdd(dl + 2, c);
+        }
+        pending = pending && !mine;
+        live = __ballot(pending);
+    }
+}
+
+// Adjoint of one pixel: d_lf[a][b] += w_ab * dimg for its K x K pairs.
+template <int KMAX>
+__device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int px, int py, int v) {
+    bool live = px < P.W && py < P.H;
+    int ia[KMAX], jb[KMAX];
+    float wa[KMAX], wb[KMAX];
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+        ia[a] = jb[a] = -1;
+        wa[a] = wb[a] = 0.0f;
+    }
+    f3 gi = mk3(0.0f, 0.0f, 0.0f);
+    float inv = 0.0f;
+    if (live) {
+        const ViewGeom& G = P.v[v];
+        const uint64_t pix = ((uint64_t)(P.view0 + v) * P.H + py) * P.W + px;
+        const float ndx = (2.0f * ((float)px + 0.5f) / (float)P.W - 1.0f) * G.sx;
+        const float ndy = (1.0f - 2.0f * ((float)py + 0.5f) / (float)P.H) * G.sy;
+        const f3 d = normalize(mk3(G.fwd[0], G.fwd[1], G.fwd[2]) + mk3(G.right[0], G.right[1], G.right[2]) * ndx +
+                               mk3(G.up[0], G.up[1], G.up[2]) * ndy);
+        const f3 oc = mk3(G.oc[0], G.oc[1], G.oc[2]);
+        const float b = dot(d, oc);
+        const float disc = b * b - G.c;
+        if (disc > P.thr) {
+            const float sq = sqrtf(disc);
+            const f3 qo = normalize(fma3(d, -b - sq, oc));
+            const f3 qd = normalize(fma3(d, -b + sq, oc));
+            float da[KMAX], db[KMAX];
+            {
+                Cand9 C;
+                sf_nearest(P.M, P.invM, qo, sf_zone(P.M, qo.z), C);
+                select_k<KMAX>(C, P.K, ia, da);
+            }
+            {
+                Cand9 C;
+                sf_nearest(P.N, P.invN, qd, sf_zone(P.N, qd.z), C);
+                select_k<KMAX>(C, P.K, jb, db);
+            }
+            const float* g = P.img + 3 * pix;
+            gi = mk3(g[0], g[1], g[2]);
+            if constexpr (KMAX == 1) {
+                wa[0] = wb[0] = 1.0f;
+                inv = 1.0f;
+            } else {
+                float wsum = 0.0f;
+#pragma unroll
+                for (int a = 0; a < KMAX; ++a) {
+                    wa[a] = ia[a] >= 0 ? tent_weight(da[a], P.inv_rM) : 0.0f;
+                    wb[a] = jb[a] >= 0 ? tent_weight(db[a], P.inv_rN) : 0.0f;
+                }
+#pragma unroll
+                for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c)
+                        wsum += (P.degenerate && ia[a] == jb[c]) ? 0.0f : wa[a] * wb[c];
+                inv = wsum > 0.0f ? 1.0f / wsum : 0.0f;
+                sort_by_index<KMAX>(ia, wa);
+                sort_by_index<KMAX>(jb, wb);
+            }
+        } else {
+            live = false;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) {
+            // nearest sampling (K = 1) copies the texel even when i == j
+            const bool bad = KMAX > 1 && P.degenerate && ia[a] == jb[c];
+            const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
+            const bool pend = live && w != 0.0f && ia[a] >= 0 && jb[c] >= 0;
+            const uint64_t key = (uint64_t)max(ia[a], 0) * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
+            wave_scatter_add(P.d_lf, pend, key, gi * w);
+        }
+}
+
 template <int KMAX, int DT, int MODE>
 __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int v = blockIdx.z;
+    if constexpr (MODE == 1) {
+        // adjoint: every lane of the wave takes part in the aggregated scatter
+        lookup_adjoint_pixel<KMAX>(P, px, py, v);
+        return;
+    }
     if (px >= P.W || py >= P.H) return;
     const ViewGeom& G = P.v[v];
     const uint64_t pix = ((uint64_t)(P.view0 + v) * P.H + py) * P.W + px;
@@ -90,12 +222,6 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
             o[0] = c.x;
             o[1] = c.y;
             o[2] = c.z;
-        } else {
-            const float* g = P.img + 3 * pix;
-            float* dl = P.d_lf + 3 * t;
-            atomicAdd(dl + 0, g[0]);
-            atomicAdd(dl + 1, g[1]);
-            atomicAdd(dl + 2, g[2]);
         }
         return;
     }
@@ -133,24 +259,6 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
         o[0] = acc.x;
         o[1] = acc.y;
         o[2] = acc.z;
-    } else {
-        if (!(wsum > 0.0f)) return;
-        const float inv = 1.0f / wsum;
-        const float* g = P.img + 3 * pix;
-        const f3 gi = mk3(g[0], g[1], g[2]);
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a)
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) {
-                const bool bad = P.degenerate && ia[a] == jb[c];
-                const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
-                if (w != 0.0f) {
-                    float* dl = P.d_lf + 3 * ((uint64_t)ia[a] * (uint64_t)P.N + (uint64_t)jb[c]);
-                    atomicAdd(dl + 0, w * gi.x);
-                    atomicAdd(dl + 1, w * gi.y);
-                    atomicAdd(dl + 2, w * gi.z);
-                }
-            }
     }
 }
 

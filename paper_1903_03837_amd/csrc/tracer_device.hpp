@@ -1,8 +1,8 @@
-// tracer_device.hpp -- the volumetric path tracer behind lf_generate and
-// lf_generate_backward.
+// tracer_device.hpp -- building blocks of the volumetric path tracer behind
+// lf_generate and lf_generate_backward (the kernel itself is in wave.hip).
 //
-// Each GPU lane owns one ray r_k of the SF ray set (Sec. 2, ray equation),
-// and traces all of its samples in order, so the FP32 sum per texel is
+// Each ray r_k of the SF ray set (Sec. 2, ray equation) is traced by one
+// lane, all of its samples in order, so the FP32 sum per texel is
 // deterministic.  Transport (the volumetric reading of Sec. 2's "conventional
 // path tracer"):
 //   - origin jitter on the disk of area 4 pi R^2 / M in the tangent plane;
@@ -17,13 +17,12 @@
 // b): pair 0 samples the light, pair 1 the phase function, then one pair per
 // shadow step (first word: distance).
 //
-// The same routine runs in three modes:
+// The kernel runs in three modes:
 //   kFwd     plain estimator;
 //   kFrozen  decisions with the sampling medium, importance weights to the
 //            evaluated medium (finite-difference hook of the adjoint);
-//   kGrad    replay of a sample whose total radiance is known: every event
-//            scatters its score times the radiance gathered after it into
-//            LDS accumulators (dLUT, dscale).
+//   kGrad    path replay: every event scatters its score times the radiance
+//            gathered after it into LDS accumulators (dLUT, dscale).
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -83,6 +82,9 @@ struct TraceParams {
     const int32_t* perm_o;
     const int32_t* perm_d;
     unsigned int* tile_ctr;
+    // adjoint: compacted list of rays with a nonzero adjoint and its length
+    uint32_t* ray_list;
+    unsigned int* ray_count;
 };
 
 struct Counters {
@@ -240,188 +242,6 @@ struct GradAcc {
         dscale = fmaf(f, t.a, dscale);
     }
 };
-
-// ---------------------------------------------------------------------------
-// One path sample of ray k = (i, j).  Returns its radiance.  In kGrad mode
-// `ltot` is this sample's radiance from a forward replay and `adj` the
-// adjoint of the texel divided by spp.
-// ---------------------------------------------------------------------------
-template <int VT, int MODE>
-__device__ f3 trace_sample(const TraceParams& P, const float4* lut_e, const float4* lut_s, float sigbar,
-                           float inv_sigbar, uint32_t k, f3 po, f3 dir, uint32_t s, Counters& cnt, f3 ltot,
-                           f3 adj, GradAcc& G) {
-    const uint32_t K0 = P.key0, K1 = P.key1;
-    f3 x = mk3(P.O[0], P.O[1], P.O[2]) + po * P.R;
-    if (P.jitter) {
-        const u4 r = philox(k, s, kPurFlight, 0, K0, K1);
-        const float rho = P.jit_rad * sqrtf(u01(r.x));
-        float sa, ca;
-        sincospif(2.0f * u01(r.y), &sa, &ca);
-        f3 t1, t2;
-        frame(po, t1, t2);
-        x = x + (t1 * (rho * ca) + t2 * (rho * sa));
-    }
-    f3 T = mk3(1.0f, 1.0f, 1.0f);
-    float W = 1.0f;
-    f3 L = mk3(0.0f, 0.0f, 0.0f);
-    const f3 env = mk3(P.env[0], P.env[1], P.env[2]);
-    cnt.samples++;
-    for (int b = 0; b < P.maxb; ++b) {
-        float tn, tf;
-        const bool hit = clip_box(P, x, dir, tn, tf);
-        bool real = false;
-        f3 y = x;
-        TF te;
-        te.l0 = 0;
-        te.w = 0.0f;
-        te.a = 0.0f;
-        te.a_s = 0.0f;
-        te.rgb = mk3(0.0f, 0.0f, 0.0f);
-        if (hit && sigbar > 0.0f) {
-            const uint32_t c2 = ((uint32_t)b << 8) | kPurFlight;
-            float t = tn;
-            bool done = false;
-            for (uint32_t blk = 0; blk < kMaxBlocks; ++blk) {
-                const u4 r = philox(k, s, c2, blk, K0, K1);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    if (b == 0 && blk == 0 && h == 0) continue;  // jitter pair
-                    const uint32_t ud = h ? r.z : r.x, ua = h ? r.w : r.y;
-                    t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
-                    if (t >= tf) {
-                        done = true;
-                        break;
-                    }
-                    cnt.tent++;
-                    y = fma3(dir, t, x);
-                    te = classify<MODE>(P, lut_e, lut_s, sample_volume<VT>(P, y));
-                    const float sig_e = P.scale_e * te.a;
-                    const float sig_s = MODE == kFrozen ? P.scale_s * te.a_s : sig_e;
-                    if (u01(ua) * sigbar < sig_s) {
-                        real = true;
-                        done = true;
-                        if constexpr (MODE == kFrozen) W *= sig_e / sig_s;
-                        if constexpr (MODE == kGrad) G.sigma(te, P.scale_e, dot(adj, ltot - L) / sig_e);
-                        break;
-                    }
-                    if constexpr (MODE == kFrozen) W *= (sigbar - sig_e) / (sigbar - sig_s);
-                    if constexpr (MODE == kGrad) G.sigma(te, P.scale_e, -dot(adj, ltot - L) / (sigbar - sig_e));
-                }
-                if (done) break;
-            }
-            if (!done) return L;  // step cap reached: absorbed
-        }
-        if (!real) {
-            L = L + T * env * W;
-            return L;
-        }
-        cnt.real++;
-        x = y;
-        const f3 rho = mk3(fminf(fmaxf(te.rgb.x, 0.0f), 1.0f), fminf(fmaxf(te.rgb.y, 0.0f), 1.0f),
-                           fminf(fmaxf(te.rgb.z, 0.0f), 1.0f));
-        if constexpr (MODE == kGrad) {
-            // albedo scores d rho_c / rho_c times the channel's later radiance
-            const f3 after = (ltot - L) * adj;
-            const float ra[3] = {te.rgb.x, te.rgb.y, te.rgb.z};
-            const float af[3] = {after.x, after.y, after.z};
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (ra[c] > 0.0f && ra[c] < 1.0f && af[c] != 0.0f) {
-                    const float f = af[c] / ra[c];
-                    atomicAdd(&G.lds[te.l0 * 4 + c], f * (1.0f - te.w));
-                    atomicAdd(&G.lds[te.l0 * 4 + 4 + c], f * te.w);
-                }
-        }
-        T = T * rho;
-        if (T.x == 0.0f && T.y == 0.0f && T.z == 0.0f) return L;
-        const u4 rv = philox(k, s, ((uint32_t)b << 8) | kPurVertex, 0, K0, K1);
-        if (P.light_on) {
-            f3 om;
-            f3 Le;
-            float tend = 0.0f;
-            if (P.light_kind == 0) {
-                om = mk3(P.ldir[0], P.ldir[1], P.ldir[2]);
-                Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]);
-                float a0, a1;
-                if (clip_box(P, x, om, a0, a1)) tend = a1;
-            } else {
-                const f3 yl = mk3(P.lcorner[0], P.lcorner[1], P.lcorner[2]) +
-                              mk3(P.le1[0], P.le1[1], P.le1[2]) * u01(rv.x) +
-                              mk3(P.le2[0], P.le2[1], P.le2[2]) * u01(rv.y);
-                const f3 v = yl - x;
-                const float dist = sqrtf(dot(v, v));
-                om = v * (1.0f / dist);
-                const float cl = fmaxf(0.0f, -dot(mk3(P.lnrm[0], P.lnrm[1], P.lnrm[2]), om));
-                const float f = cl * P.larea / (dist * dist);
-                Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * f;
-                float a0, a1;
-                tend = dist;
-                if (clip_box(P, x, om, a0, a1)) tend = fminf(tend, a1);
-                else tend = 0.0f;
-            }
-            float Tr = 1.0f;
-            if (sigbar > 0.0f) {
-                const uint32_t c2 = ((uint32_t)b << 8) | kPurVertex;
-                float t = 0.0f;
-                bool done = false;
-                for (uint32_t blk = 1; blk < kMaxBlocks; ++blk) {
-                    const u4 r = philox(k, s, c2, blk, K0, K1);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const uint32_t ud = h ? r.z : r.x;
-                        t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
-                        if (t >= tend) {
-                            done = true;
-                            break;
-                        }
-                        cnt.shadow++;
-                        const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT>(P, fma3(om, t, x)));
-                        Tr *= 1.0f - P.scale_e * ts.a * inv_sigbar;
-                    }
-                    if (done) break;
-                }
-                if (!done) Tr = 0.0f;  // step cap reached: blocked
-            }
-            const float fp = hg_phase(P.g, dot(dir, om));
-            const f3 C = T * Le * (W * fp * Tr);
-            if constexpr (MODE == kGrad) {
-                // ratio-tracking scores -d sigma / (sigma_bar - sigma) times this
-                // NEE term only: replay the shadow steps now that Tr is known
-                const float rc = dot(adj, C);
-                if (rc != 0.0f && sigbar > 0.0f) {
-                    const uint32_t c2 = ((uint32_t)b << 8) | kPurVertex;
-                    float t = 0.0f;
-                    for (uint32_t blk = 1; blk < kMaxBlocks; ++blk) {
-                        const u4 r = philox(k, s, c2, blk, K0, K1);
-                        bool done = false;
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const uint32_t ud = h ? r.z : r.x;
-                            t = fmaf(neg_log1m(u01(ud)), inv_sigbar, t);
-                            if (t >= tend) {
-                                done = true;
-                                break;
-                            }
-                            const TF ts = classify<MODE>(P, lut_e, lut_s, sample_volume<VT>(P, fma3(om, t, x)));
-                            G.sigma(ts, P.scale_e, -rc / (sigbar - P.scale_e * ts.a));
-                        }
-                        if (done) break;
-                    }
-                }
-            }
-            L = L + C;
-        }
-        if (b == P.maxb - 1) return L;
-        const float mu = hg_mu(P.g, u01(rv.z));
-        const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
-        float sp, cp;
-        sincospif(2.0f * u01(rv.w), &sp, &cp);
-        f3 t1, t2;
-        frame(dir, t1, t2);
-        dir = t1 * (st * cp) + t2 * (st * sp) + dir * mu;
-    }
-    return L;
-}
 
 // ---------------------------------------------------------------------------
 // Texel store (FP32 / FP16 / BF16, round to nearest even) and wave sums

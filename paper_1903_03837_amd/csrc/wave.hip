@@ -1,5 +1,5 @@
-// wave.hip -- persistent light-field generation kernel (forward and frozen
-// sampling modes).
+// wave.hip -- persistent light-field generation kernel (forward, frozen
+// sampling, and the path-replay adjoint).
 //
 // Paths differ wildly in cost: a ray that misses the volume is done after
 // one clip, a ray through dense tissue scatters and casts shadow rays.  With
@@ -26,11 +26,21 @@
 // the XCDs), so each XCD's L2 sees a narrow bundle of rays.  A part that runs
 // dry hands out tiles of the next parts.  Results do not depend on the order:
 // every random number is keyed by (ray, sample, bounce).
+//
+// Adjoint mode: the rays with a nonzero adjoint are first compacted into a
+// list (in the same spatial order) and the waves take 64-ray chunks of that
+// list.  Every sample runs twice: pass A gathers its radiance L_tot, pass B
+// replays the same stream and, at every event, adds the event's score times
+// the radiance gathered after it (adjoint . (L_tot - L_so_far)) to per-
+// workgroup LDS gradients: real collision d sigma / sigma, null collision and
+// ratio-tracking step -d sigma / (sigma_bar - sigma), albedo d rho / rho.  A
+// shadow ray in pass B runs twice (transmittance first, then its scores,
+// which multiply only its own NEE term).  Nothing is stored per path.
 #include "internal.hpp"
 
 namespace lp {
 
-enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4 };
+enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4, kShadow2 = 5 };
 constexpr int kGroupTiles = 16;
 constexpr int kParts = 8;
 
@@ -68,10 +78,13 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
     extern __shared__ float4 smem[];
     float4* lut_e = smem;
     float4* lut_s = smem + (MODE == kFrozen ? P.lut_n : 0);
+    float* glds = (float*)(smem + P.lut_n);  // kGrad: dLUT [lut_n][4], dscale
     for (int e = threadIdx.x; e < P.lut_n; e += blockDim.x) {
         lut_e[e] = ((const float4*)P.lut_e)[e];
         if constexpr (MODE == kFrozen) lut_s[e] = ((const float4*)P.lut_s)[e];
     }
+    if constexpr (MODE == kGrad)
+        for (int e = threadIdx.x; e < 4 * P.lut_n + 1; e += blockDim.x) glds[e] = 0.0f;
     __syncthreads();
 
     const float sigbar = *P.sigbar;
@@ -80,7 +93,9 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
     const int lane = threadIdx.x & 63;
     const int rows = P.row_end - P.row_begin;
     const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
-    const long long ntiles = (long long)tiles_i * tiles_j;
+    const long long nlist = MODE == kGrad ? (long long)*P.ray_count : 0;
+    const long long ntiles = MODE == kGrad ? (nlist + 63) / 64 : (long long)tiles_i * tiles_j;
+    const float inv_spp = 1.0f / (float)P.spp;
     const int home = blockIdx.x % kParts;
     const float invM = 1.0f / (float)P.M, invN = 1.0f / (float)P.N;
     const f3 O = mk3(P.O[0], P.O[1], P.O[2]);
@@ -99,6 +114,15 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
     f3 po = mk3(0, 0, 0), d0 = po, acc = po, x = po, dir = po, T = po, L = po, om = po, C = po;
     float W = 1.0f, t = 0.0f, tend = 0.0f, Tr = 1.0f, up0 = 0.0f, up1 = 0.0f;
     Counters cnt = {0, 0, 0, 0};
+    // adjoint state: texel adjoint / spp, pass A radiance, pass, NEE score weight
+    f3 adj = po, ltot = po;
+    int pass = 0;
+    float rc = 0.0f;
+    GradAcc G;
+    G.lds = glds;
+    G.cl0 = -1;
+    G.c0 = G.c1 = 0.0f;
+    G.dscale = 0.0f;
 
     for (;;) {
         // ------------------------------------------------------------ refill
@@ -128,14 +152,30 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                 cur += min((long long)nidle, avail);
             }
             if (q >= 0) {
-                int ti, tj;
-                tile_coords(q >> 6, tiles_i, tiles_j, ti, tj);
-                const int oi = ti * 8 + (int)((q >> 3) & 7), dj = tj * 8 + (int)(q & 7);
-                if (oi < rows && dj < P.N) {
-                    const int i = P.perm_o[oi], j = P.perm_d[dj];
+                int i = -1, j = -1;
+                if constexpr (MODE == kGrad) {
+                    if (q < nlist) {
+                        const uint32_t kk = P.ray_list[q];
+                        i = (int)(kk / (uint32_t)P.N);
+                        j = (int)(kk - (uint32_t)i * (uint32_t)P.N);
+                        const float* a = P.d_lf + 3 * (uint64_t)kk;
+                        adj = mk3(a[0] * inv_spp, a[1] * inv_spp, a[2] * inv_spp);
+                        pass = 0;
+                    }
+                } else {
+                    int ti, tj;
+                    tile_coords(q >> 6, tiles_i, tiles_j, ti, tj);
+                    const int oi = ti * 8 + (int)((q >> 3) & 7), dj = tj * 8 + (int)(q & 7);
+                    if (oi < rows && dj < P.N) {
+                        i = P.perm_o[oi];
+                        j = P.perm_d[dj];
+                    }
+                }
+                if (i >= 0) {
                     k = (uint32_t)i * (uint32_t)P.N + (uint32_t)j;
                     if (P.M == P.N && i == j) {
-                        store_texel(P, k, mk3(0.0f, 0.0f, 0.0f));  // no direction: texel 0
+                        // no direction: texel 0 (never listed for the adjoint)
+                        if constexpr (MODE != kGrad) store_texel(P, k, mk3(0.0f, 0.0f, 0.0f));
                     } else {
                         po = sf_point(P.M, i, invM);
                         d0 = normalize(sf_point(P.N, j, invN) - po);
@@ -154,9 +194,9 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
         }
 
         // ------------------------------------------------------ one block
-        const bool vstream = mode == kVertex || mode == kShadow;
+        const bool vstream = mode == kVertex || mode == kShadow || mode == kShadow2;
         const u4 r = philox(k, (uint32_t)s, ((uint32_t)b << 8) | (vstream ? kPurVertex : kPurFlight), blk, K0, K1);
-        bool stepA = mode == kFlight || mode == kShadow;
+        bool stepA = mode == kFlight || mode == kShadow || mode == kShadow2;
         bool stepB = stepA;
         bool sample_done = false, after_shadow = false;
 
@@ -236,7 +276,7 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
         te.a = te.a_s = 0.0f;
         te.rgb = mk3(0.0f, 0.0f, 0.0f);
         if (stepA || stepB) {
-            const f3 sd = mode == kShadow ? om : dir;
+            const f3 sd = mode == kFlight ? dir : om;
             const float tA = fmaf(neg_log1m(u01(r.x)), inv_sigbar, t);
             const float tB = fmaf(neg_log1m(u01(r.z)), inv_sigbar, stepA ? tA : t);
             const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
@@ -265,24 +305,56 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                         ynew = h ? yB : yA;
                         te = tf;
                         if constexpr (MODE == kFrozen) W *= sig_e / sig_s;
+                        if constexpr (MODE == kGrad)
+                            if (pass) G.sigma(tf, P.scale_e, dot(adj, ltot - L) / sig_e);
                     } else {
                         if constexpr (MODE == kFrozen) W *= (sigbar - sig_e) / (sigbar - sig_s);
+                        if constexpr (MODE == kGrad)
+                            if (pass) G.sigma(tf, P.scale_e, -dot(adj, ltot - L) / (sigbar - sig_e));
                     }
-                } else {
+                } else if (mode == kShadow) {
                     cnt.shadow++;
                     Tr *= 1.0f - sig_e * inv_sigbar;
+                } else {
+                    if constexpr (MODE == kGrad) G.sigma(tf, P.scale_e, -rc / (sigbar - sig_e));
                 }
             }
             if (ev_end) {
                 if (mode == kFlight) {
                     L = L + T * env * W;
                     sample_done = true;
+                } else if (MODE == kGrad && mode == kShadow && pass) {
+                    // transmittance known: replay the shadow ray for its scores
+                    rc = dot(adj, C * Tr);
+                    if (rc != 0.0f) {
+                        mode = kShadow2;
+                        blk = 1;
+                        t = 0.0f;
+                    } else {
+                        L = L + C * Tr;
+                        after_shadow = true;
+                    }
                 } else {
                     L = L + C * Tr;
                     after_shadow = true;
                 }
             } else if (ev_real) {
                 cnt.real++;
+                if constexpr (MODE == kGrad) {
+                    if (pass) {
+                        // albedo scores d rho_c / rho_c times the channel's later radiance
+                        const f3 after = (ltot - L) * adj;
+                        const float ra[3] = {te.rgb.x, te.rgb.y, te.rgb.z};
+                        const float af[3] = {after.x, after.y, after.z};
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            if (ra[c] > 0.0f && ra[c] < 1.0f && af[c] != 0.0f) {
+                                const float f = af[c] / ra[c];
+                                atomicAdd(&glds[te.l0 * 4 + c], f * (1.0f - te.w));
+                                atomicAdd(&glds[te.l0 * 4 + 4 + c], f * te.w);
+                            }
+                    }
+                }
                 x = ynew;
                 T = T * mk3(fminf(fmaxf(te.rgb.x, 0.0f), 1.0f), fminf(fmaxf(te.rgb.y, 0.0f), 1.0f),
                             fminf(fmaxf(te.rgb.z, 0.0f), 1.0f));
@@ -294,8 +366,12 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                 }
             } else if (++blk >= kMaxBlocks) {
                 // stream exhausted: the segment ends absorbed / blocked
-                if (mode == kFlight) sample_done = true;
-                else after_shadow = true;
+                if (mode == kFlight) {
+                    sample_done = true;
+                } else {
+                    Tr = 0.0f;  // C * 0 adds nothing
+                    after_shadow = true;
+                }
             }
         }
 
@@ -327,10 +403,23 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
 
         // ------------------------------------------------------ sample end
         if (sample_done) {
-            acc = acc + L;
-            if (++s == P.spp) {
-                const float fs = (float)P.spp;
-                store_texel(P, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
+            bool next = true;
+            if constexpr (MODE == kGrad) {
+                if (pass == 0) {  // replay the same sample with scores
+                    ltot = L;
+                    pass = 1;
+                    next = false;
+                } else {
+                    pass = 0;
+                }
+            } else {
+                acc = acc + L;
+            }
+            if (next && ++s == P.spp) {
+                if constexpr (MODE != kGrad) {
+                    const float fs = (float)P.spp;
+                    store_texel(P, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
+                }
                 mode = kIdle;
             } else {
                 mode = kStart;
@@ -338,6 +427,17 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                 blk = 0;
             }
         }
+    }
+
+    if constexpr (MODE == kGrad) {
+        G.flush();
+        const float ds = wave_sumf(G.dscale);
+        if (lane == 0) atomicAdd(&glds[4 * P.lut_n], ds);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 4 * P.lut_n; e += blockDim.x)
+            if (glds[e] != 0.0f) atomicAdd(&P.d_lut[e], glds[e]);
+        if (threadIdx.x == 0 && glds[4 * P.lut_n] != 0.0f) atomicAdd(P.d_scale, glds[4 * P.lut_n]);
+        return;
     }
 
     if (P.stats) {
@@ -368,13 +468,44 @@ __global__ void sf_order_kernel(int base, int count, int band, int32_t* out) {
     out[lo + rank] = base + e;
 }
 
+// Compacts the rays (in the spatial tile order) whose adjoint is nonzero.
+__global__ void active_rays_kernel(TraceParams P) {
+    const int rows = P.row_end - P.row_begin;
+    const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
+    const long long total = (long long)tiles_i * tiles_j * 64;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < total; base += stride) {
+        const long long q = base + threadIdx.x;
+        bool take = false;
+        uint32_t k = 0;
+        if (q < total) {
+            int ti, tj;
+            tile_coords(q >> 6, tiles_i, tiles_j, ti, tj);
+            const int oi = ti * 8 + (int)((q >> 3) & 7), dj = tj * 8 + (int)(q & 7);
+            if (oi < rows && dj < P.N) {
+                const int i = P.perm_o[oi], j = P.perm_d[dj];
+                k = (uint32_t)i * (uint32_t)P.N + (uint32_t)j;
+                const float* a = P.d_lf + 3 * (uint64_t)k;
+                take = !(P.M == P.N && i == j) && (a[0] != 0.0f || a[1] != 0.0f || a[2] != 0.0f);
+            }
+        }
+        const uint64_t m = __ballot(take);
+        unsigned at = 0;
+        if (lane == 0 && m) at = atomicAdd(P.ray_count, (unsigned)__popcll(m));
+        at = __shfl(at, 0, 64);
+        if (take) P.ray_list[at + __popcll(m & lt_mask)] = k;
+    }
+}
+
 __global__ void wave_setup_kernel(const float* lut, int n, float scale, float given, float* sigbar,
                                   unsigned int* ctr) {
     __shared__ float red[256];
     float m = 0.0f;
     for (int e = threadIdx.x; e < n; e += 256) m = fmaxf(m, lut[4 * e + 3]);
     red[threadIdx.x] = m;
-    if (threadIdx.x < kParts) ctr[threadIdx.x] = 0u;
+    if (threadIdx.x < kParts + 1) ctr[threadIdx.x] = 0u;  // tile counters, then the list length
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
@@ -399,12 +530,23 @@ hipError_t launch_wave_setup(const TraceParams& P, const float* sample_lut, int 
     return hipGetLastError();
 }
 
+hipError_t launch_active_rays(const TraceParams& P, hipStream_t s) {
+    const long long rows = P.row_end - P.row_begin;
+    const long long total = ((rows + 7) / 8) * (long long)((P.N + 7) / 8) * 64;
+    if (total <= 0) return hipSuccess;
+    long long blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    active_rays_kernel<<<(unsigned)blocks, 256, 0, s>>>(P);
+    return hipGetLastError();
+}
+
 template <int VT, int MODE>
 static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
     const long long ntiles = ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
     if (ntiles <= 0) return hipSuccess;
-    const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1);
+    const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
+                       (MODE == kGrad ? sizeof(float) * (4 * (size_t)P.lut_n + 1) : 0);
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -412,7 +554,9 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE>, 256, lds);
     if (e != hipSuccess) return e;
     long long blocks = (long long)cus * (per_cu > 0 ? per_cu : 1);
-    const long long need = (ntiles + 3) / 4;  // at least one tile per wave
+    // at least one tile per wave (the adjoint's list length is only known on
+    // the device; its waves that find no chunk exit at once)
+    const long long need = (ntiles + 3) / 4;
     if (blocks > need) blocks = need;
     gen_wave_kernel<VT, MODE><<<(unsigned)blocks, 256, lds, s>>>(P);
     return hipGetLastError();
@@ -420,6 +564,7 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
 
 template <int VT>
 static hipError_t launch_wave_mode(const TraceParams& P, int mode, hipStream_t s) {
+    if (mode == kGrad) return launch_wave_t<VT, kGrad>(P, s);
     return mode == kFrozen ? launch_wave_t<VT, kFrozen>(P, s) : launch_wave_t<VT, kFwd>(P, s);
 }
 

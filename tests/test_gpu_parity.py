@@ -317,8 +317,9 @@ def test_lookup_c2_full_size_sampled(lp, orc):
     check_pixels(g_img[clear], rgb[clear], tol)
 
 
-def test_lookup_adjoint(lp, orc):
-    M, N, V, W, H, K = 96, 80, 2, 40, 30, 5
+@pytest.mark.parametrize("M,N,K", [(96, 80, 5), (64, 64, 5), (64, 64, 1), (96, 80, 9)])
+def test_lookup_adjoint(lp, orc, M, N, K):
+    V, W, H = 2, 40, 30
     sc = S.config(1, M=M, N=N, views=V, width=W, height=H)
     prm = lp.GenParams(M=M, N=N, radius=sc.params.radius)
     cams = [lp.Camera(c.eye, c.target, c.up, c.vfov) for c in sc.cams]
