@@ -167,6 +167,8 @@ def main():
     log("bench: legs (ms) " + ", ".join(f"{k} {v:.2f}" for k, v in legs.items()))
 
     gen_s = legs["generate"] / 1e3
+    # voxel bytes the estimator reads: 8 voxels per tentative point (u16)
+    tent_bytes = (tent + shadow) * 8 * 2
     achieved = alg_ops / gen_s
     khash = kernel_source_hash()
     traffic = measured_traffic(khash)
@@ -215,6 +217,9 @@ def main():
             "unit": "Top/s (32-bit lane ops)",
             "frac": achieved / PEAK_OPS,
             "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_GBps": (traffic / gen_s / 1e9) if traffic else None,
+            "gather_GBps": tent_bytes / gen_s / 1e9,
             "launch_ms": legs["generate"],
             "ops_per_launch": alg_ops,
             "units_per_launch": {"tentative_collisions": tent, "shadow_steps": shadow, "real_collisions": real,

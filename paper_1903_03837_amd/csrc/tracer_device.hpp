@@ -87,6 +87,12 @@ struct TraceParams {
     unsigned int* ray_count;
 };
 
+// Hardware reciprocal / reciprocal square root (1 ulp).  Used where the
+// result only moves a continuous quantity (slab bounds, frames, directions);
+// the texel mean and the importance weights keep IEEE division.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 struct Counters {
     uint32_t tent, shadow, real, samples;
 };
@@ -161,17 +167,18 @@ __device__ __forceinline__ TF classify(const TraceParams& P, const float4* lut_e
 // Geometry
 // ---------------------------------------------------------------------------
 // [tn, tf) of o + t d, t >= 0, inside the box; false when empty.
-__device__ __forceinline__ bool clip_box(const TraceParams& P, f3 o, f3 d, float& tn, float& tf) {
+__device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, float& tn, float& tf) {
     float t0 = 0.0f, t1 = 3.402823466e38f;
     const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+    const float lo[3] = {bmin.x, bmin.y, bmin.z}, hi[3] = {bmax.x, bmax.y, bmax.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (dd[a] == 0.0f) {
-            if (oo[a] < P.bmin[a] || oo[a] > P.bmax[a]) return false;
+            if (oo[a] < lo[a] || oo[a] > hi[a]) return false;
             continue;
         }
-        const float inv = 1.0f / dd[a];
-        float ta = (P.bmin[a] - oo[a]) * inv, tb = (P.bmax[a] - oo[a]) * inv;
+        const float inv = rcp(dd[a]);
+        float ta = (lo[a] - oo[a]) * inv, tb = (hi[a] - oo[a]) * inv;
         if (ta > tb) {
             const float t = ta;
             ta = tb;
@@ -188,7 +195,7 @@ __device__ __forceinline__ bool clip_box(const TraceParams& P, f3 o, f3 d, float
 // Orthonormal completion of unit n (Duff et al. 2017).
 __device__ __forceinline__ void frame(f3 n, f3& t1, f3& t2) {
     const float sg = n.z >= 0.0f ? 1.0f : -1.0f;
-    const float a = -1.0f / (sg + n.z);
+    const float a = -rcp(sg + n.z);
     const float b = n.x * n.y * a;
     t1 = mk3(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
     t2 = mk3(b, sg + n.y * n.y * a, -n.y);
@@ -196,7 +203,7 @@ __device__ __forceinline__ void frame(f3 n, f3& t1, f3& t2) {
 
 __device__ __forceinline__ float hg_phase(float g, float mu) {
     const float den = 1.0f + g * g - 2.0f * g * mu;
-    const float r = 1.0f / sqrtf(den);
+    const float r = rsq(den);
     return (1.0f - g * g) * 0.0795774715459476679f * r * r * r;
 }
 __device__ __forceinline__ float hg_mu(float g, float u) {
@@ -204,8 +211,8 @@ __device__ __forceinline__ float hg_mu(float g, float u) {
     if (fabsf(g) < 1e-3f) {
         mu = 1.0f - 2.0f * u;
     } else {
-        const float s = (1.0f - g * g) / (1.0f - g + 2.0f * g * u);
-        mu = (1.0f + g * g - s * s) / (2.0f * g);
+        const float s = (1.0f - g * g) * rcp(1.0f - g + 2.0f * g * u);
+        mu = (1.0f + g * g - s * s) * rcp(2.0f * g);
     }
     return fminf(fmaxf(mu, -1.0f), 1.0f);
 }
@@ -252,19 +259,19 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ void store_texel(const TraceParams& P, uint64_t k, f3 v) {
-    if (P.dtype == 0) {
-        float* o = (float*)P.out + 3 * k;
+__device__ __forceinline__ void store_texel(void* out, int dtype, uint64_t k, f3 v) {
+    if (dtype == 0) {
+        float* o = (float*)out + 3 * k;
         o[0] = v.x;
         o[1] = v.y;
         o[2] = v.z;
-    } else if (P.dtype == 1) {
-        __half* o = (__half*)P.out + 3 * k;
+    } else if (dtype == 1) {
+        __half* o = (__half*)out + 3 * k;
         o[0] = __float2half_rn(v.x);
         o[1] = __float2half_rn(v.y);
         o[2] = __float2half_rn(v.z);
     } else {
-        uint16_t* o = (uint16_t*)P.out + 3 * k;
+        uint16_t* o = (uint16_t*)out + 3 * k;
         o[0] = bf16_rne(v.x);
         o[1] = bf16_rne(v.y);
         o[2] = bf16_rne(v.z);

@@ -95,11 +95,12 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
     const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
     const long long nlist = MODE == kGrad ? (long long)*P.ray_count : 0;
     const long long ntiles = MODE == kGrad ? (nlist + 63) / 64 : (long long)tiles_i * tiles_j;
-    const float inv_spp = 1.0f / (float)P.spp;
     const int home = blockIdx.x % kParts;
+    const float inv_spp = 1.0f / (float)P.spp;
     const float invM = 1.0f / (float)P.M, invN = 1.0f / (float)P.N;
     const f3 O = mk3(P.O[0], P.O[1], P.O[2]);
     const f3 env = mk3(P.env[0], P.env[1], P.env[2]);
+    const f3 bmin = mk3(P.bmin[0], P.bmin[1], P.bmin[2]), bmax = mk3(P.bmax[0], P.bmax[1], P.bmax[2]);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     // wave-uniform queue cursor: rays [cur, end) of the current tile
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                     k = (uint32_t)i * (uint32_t)P.N + (uint32_t)j;
                     if (P.M == P.N && i == j) {
                         // no direction: texel 0 (never listed for the adjoint)
-                        if constexpr (MODE != kGrad) store_texel(P, k, mk3(0.0f, 0.0f, 0.0f));
+                        if constexpr (MODE != kGrad) store_texel(P.out, P.dtype, k, mk3(0.0f, 0.0f, 0.0f));
                     } else {
                         po = sf_point(P.M, i, invM);
                         d0 = normalize(sf_point(P.N, j, invN) - po);
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
             W = 1.0f;
             L = mk3(0.0f, 0.0f, 0.0f);
             float tn, tf;
-            if (clip_box(P, x, dir, tn, tf) && sigbar > 0.0f) {
+            if (clip_box(bmin, bmax, x, dir, tn, tf) && sigbar > 0.0f) {
                 t = tn;
                 tend = tf;
                 mode = kFlight;
@@ -236,19 +237,21 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                     om = mk3(P.ldir[0], P.ldir[1], P.ldir[2]);
                     Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]);
                     float a0, a1;
-                    if (clip_box(P, x, om, a0, a1)) te = a1;
+                    if (clip_box(bmin, bmax, x, om, a0, a1)) te = a1;
                 } else {
                     const f3 yl = mk3(P.lcorner[0], P.lcorner[1], P.lcorner[2]) +
                                   mk3(P.le1[0], P.le1[1], P.le1[2]) * u01(r.x) +
                                   mk3(P.le2[0], P.le2[1], P.le2[2]) * u01(r.y);
                     const f3 v = yl - x;
-                    const float dist = sqrtf(dot(v, v));
-                    om = v * (1.0f / dist);
+                    const float d2 = dot(v, v);
+                    const float rinv = rsq(d2);
+                    const float dist = d2 * rinv;
+                    om = v * rinv;
                     const float cl = fmaxf(0.0f, -dot(mk3(P.lnrm[0], P.lnrm[1], P.lnrm[2]), om));
-                    Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * (cl * P.larea / (dist * dist));
+                    Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * (cl * P.larea * rcp(d2));
                     float a0, a1;
                     te = dist;
-                    if (clip_box(P, x, om, a0, a1)) te = fminf(te, a1);
+                    if (clip_box(bmin, bmax, x, om, a0, a1)) te = fminf(te, a1);
                     else te = 0.0f;
                 }
                 C = T * Le * (W * hg_phase(P.g, dot(dir, om)));
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                 dir = t1 * (st * cp) + t2 * (st * sp) + dir * mu;
                 ++b;
                 float tn, tf;
-                if (clip_box(P, x, dir, tn, tf) && sigbar > 0.0f) {
+                if (clip_box(bmin, bmax, x, dir, tn, tf) && sigbar > 0.0f) {
                     t = tn;
                     tend = tf;
                     mode = kFlight;
@@ -418,7 +421,7 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
             if (next && ++s == P.spp) {
                 if constexpr (MODE != kGrad) {
                     const float fs = (float)P.spp;
-                    store_texel(P, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
+                    store_texel(P.out, P.dtype, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
                 }
                 mode = kIdle;
             } else {
