@@ -179,18 +179,22 @@ def phantom_volume(n: int, seed: int, n_ellipsoids: int, noise: float = 20.0,
     for z0 in range(0, n, chunk):
         z1 = min(n, z0 + chunk)
         hu = np.full((z1 - z0, n, n), -1000.0, dtype=np.float32)
-        zz, yy, xx = np.meshgrid(idx[z0:z1], idx, idx, indexing="ij")
         for c, rot, a, h in ells:
             r = a.max()
             if c[2] + r < z0 or c[2] - r > z1:
                 continue
+            zlo, zhi = max(z0, int(c[2] - r) - 1), min(z1, int(c[2] + r) + 2)
             ylo, yhi = max(0, int(c[1] - r) - 1), min(n, int(c[1] + r) + 2)
             xlo, xhi = max(0, int(c[0] - r) - 1), min(n, int(c[0] + r) + 2)
-            sub = (slice(None), slice(ylo, yhi), slice(xlo, xhi))
-            p = np.stack([xx[sub] - c[0], yy[sub] - c[1], zz[sub] - c[2]], -1).astype(np.float32)
-            d = p @ rot.astype(np.float32)
-            inside = np.sum((d / a.astype(np.float32)) ** 2, -1) <= 1.0
-            hu[sub][inside] = h
+            if zlo >= zhi:
+                continue
+            dz = (idx[zlo:zhi] - c[2])[:, None, None]
+            dy = (idx[ylo:yhi] - c[1])[None, :, None]
+            dx = (idx[xlo:xhi] - c[0])[None, None, :]
+            q = np.zeros((zhi - zlo, yhi - ylo, xhi - xlo), dtype=np.float32)
+            for k in range(3):  # rotated coordinate k over its semi-axis
+                q += ((rot[0, k] * dx + rot[1, k] * dy + rot[2, k] * dz) / a[k]).astype(np.float32) ** 2
+            hu[zlo - z0:zhi - z0, ylo:yhi, xlo:xhi][q <= 1.0] = h
         hu += rng.standard_normal(hu.shape, dtype=np.float32) * noise
         out[z0:z1] = np.clip(np.rint(hu + 1024.0), 0, 65535).astype(np.uint16)
     return out
