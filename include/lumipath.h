@@ -93,12 +93,17 @@ typedef struct {
  * radius R = radius; P_o of M points, P_d of N points; ray k = i*N + j runs
  * from O + R p_i towards O + R p_j with its origin jittered on the disk of
  * area 4 pi R^2 / M when jitter != 0).  M, N in [1, 65535], M*N < 2^32.
+ * origin_rows (0 = M) keeps only the origins i < origin_rows: the light field
+ * is stored as [origin_rows][N][3].  Heights of the SF set fall with i, so
+ * origin_rows = M/2 keeps the upper hemisphere (Sec. 3 stores P_o that way,
+ * halving the texture); lookups whose front hit has no stored origin are
+ * uncovered (pixel 0).
  * spp >= 1 samples, 1 <= max_bounces <= 65535 scatter vertices, |hg_g| < 1.
  * majorant <= 0 selects 1.25 * density_scale * max alpha of the sampling
- * medium.  Rows [row_begin, row_end) of i are generated (row_end <= 0: M);
- * results do not depend on this split.  stats: NULL or device uint64[4]
- * incremented by [tentative collisions, shadow-ray steps, real collisions,
- * path samples]. */
+ * medium.  Rows [row_begin, row_end) of i are generated (row_end <= 0:
+ * origin_rows); results do not depend on this split.  stats: NULL or device
+ * uint64[4] incremented by [tentative collisions, shadow-ray steps, real
+ * collisions, path samples]. */
 typedef struct {
     int32_t M, N;
     float center[3];
@@ -108,7 +113,7 @@ typedef struct {
     float majorant;
     uint64_t seed;
     int32_t jitter;
-    int32_t reserved;
+    int32_t origin_rows;    /* stored origin rows: 0 = M; M/2 keeps the upper hemisphere */
     int64_t row_begin, row_end;
     uint64_t* stats;
 } lf_gen_params;
@@ -140,7 +145,7 @@ int lf_points(int32_t n, float* xyz_out, const float* query, int64_t nq, int32_t
 
 /* Light-field generation (Sec. 2, Fig. 1): writes Lhat(i, j) = mean over spp
  * path samples of the radiance along ray k = i*N + j, for rows
- * [row_begin, row_end), into lf_out ([M][N][3] of `dtype`).  Texels with
+ * [row_begin, row_end), into lf_out ([origin_rows][N][3] of `dtype`).  Texels with
  * M == N and i == j (no direction) are 0.  Random numbers: Philox4x32-10
  * keyed by `seed`, counter (k, sample, bounce << 8 | purpose, block), so the
  * result is independent of launch shape and row split.
@@ -157,11 +162,13 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
  * of n_views W x H views: the view ray's front and back hits on S (tangential
  * rays discarded) are mapped to their K nearest points of P_o and P_d and the
  * K x K texels blended with normalised tent weights (pairs i == j excluded
- * when M == N); K = 1 is nearest sampling.  Uses M, N, center, radius of
- * params.
+ * when M == N); K = 1 is nearest sampling.  Uses M, N, origin_rows, center,
+ * radius of params; neighbours i >= origin_rows are not stored and get weight
+ * 0 (a pixel with none left is 0).
  *   mode LF_LOOKUP_FORWARD: lf (dtype) -> img float [n_views][H][W][3].
  *   mode LF_LOOKUP_ADJOINT: img holds d(loss)/d(img); d_lf (float32
- *        [M][N][3]) is incremented by its transpose (atomics; lf unused).
+ *        [origin_rows][N][3]) is incremented by its transpose (atomics; lf
+ *        unused).
  *   nn_out: NULL or int32 [n_views][H][W][2], nearest (i, j), -1 on a miss.
  *   cams: host array of n_views cameras, each eye outside S. */
 int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams,
@@ -169,7 +176,7 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
               float* d_lf, int32_t* nn_out, void* stream);
 
 /* Adjoint of lf_generate (path-replay extension): given d_lf = d(loss)/d(Lhat)
- * (float32 [M][N][3]), overwrites d_lut (float32 [lut_size][4]) and d_scale
+ * (float32 [origin_rows][N][3]), overwrites d_lut (float32 [lut_size][4]) and d_scale
  * (float32 [1]) with d(loss)/d(LUT) and d(loss)/d(density_scale) of the
  * estimator for the same random stream, majorant held fixed.  Each sample is
  * traced twice (total radiance, then scores times radiance gathered after

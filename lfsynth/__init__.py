@@ -69,6 +69,7 @@ class Params:
     majorant: float = 0.0     # <= 0: 1.25 * scale * max alpha
     seed: int = 0
     jitter: int = 1
+    origin_rows: int = 0      # 0: all M origins; M // 2: upper hemisphere only
 
 
 @dataclass
@@ -248,6 +249,19 @@ def cameras(seed: int, count: int, radius: float, center: Vec3 = (0.0, 0.0, 0.0)
         up = (0.0, 0.0, 1.0) if abs(d[2]) < 0.99 else (1.0, 0.0, 0.0)
         out.append(Camera(eye=tuple(eye), target=tuple(center), up=up,
                           vfov=2.0 * math.asin(radius / dist) * 1.05))
+    return out
+
+
+def seam_cameras(radius: float, center: Vec3 = (0.0, 0.0, 0.0)) -> List[Camera]:
+    """Three views from near the equator plane (elevations 0.15, -0.2, 0 rad)
+    at distance 3R: their front hits cover both hemispheres of S and the seam
+    between them (cases for a light field that stores only the upper half of
+    the origins)."""
+    out = []
+    for az, el in ((0.3, 0.15), (2.1, -0.2), (4.0, 0.0)):
+        d = np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+        out.append(Camera(eye=tuple(np.asarray(center) + 3.0 * radius * d), target=tuple(center),
+                          up=(0.0, 0.0, 1.0), vfov=2.0 * math.asin(1.0 / 3.0) * 1.05))
     return out
 
 

@@ -734,16 +734,21 @@ static void query_pixel(const orc_params* P, const orc_camera* cam, int32_t W, i
     q->margin[3] = fmin(mo[2] / ao, md[2] / ad);
 }
 
+static int64_t stored_rows(const orc_params* P) { return P->origin_rows > 0 ? P->origin_rows : P->M; }
+
 /* Normalised pair weights w_o(a) w_d(b) / sum; pairs with a == b are the
- * undefined texels of P_o = P_d and get weight 0.  K = 1 is nearest
- * sampling: the single texel, unweighted. */
+ * undefined texels of P_o = P_d and get weight 0, and so do origins that are
+ * not stored.  K = 1 is nearest sampling: the single texel, unweighted, if
+ * its origin is stored. */
 static int pair_weights(const orc_params* P, int32_t K, const pixel_query* q, double* wab) {
-    if (K == 1) { wab[0] = 1.0; return 1; }
+    const int64_t rows = stored_rows(P);
+    if (K == 1) { wab[0] = 1.0; return q->ia[0] < rows; }
     double sum = 0.0;
     for (int a = 0; a < q->na; ++a)
         for (int b = 0; b < q->nb; ++b) {
             double w = q->wa[a] * q->wb[b];
             if (P->M == P->N && q->ia[a] == q->jb[b]) w = 0.0;
+            if (q->ia[a] >= rows) w = 0.0;
             wab[a * 9 + b] = w;
             sum += w;
         }
@@ -773,12 +778,10 @@ static void* lookup_worker(void* arg) {
             if (jb->nn) { jb->nn[2 * p] = -1; jb->nn[2 * p + 1] = -1; }
         } else {
             if (jb->nn) { jb->nn[2 * p] = q.ia[0]; jb->nn[2 * p + 1] = q.jb[0]; }
-            if (jb->K == 1) {
-                const float* t = jb->lf + 3 * (q.ia[0] * P->N + q.jb[0]);
-                for (int c = 0; c < 3; ++c) out[c] = (double)t[c];
-            } else if (pair_weights(P, jb->K, &q, wab)) {
+            if (pair_weights(P, jb->K, &q, wab)) {
                 for (int a = 0; a < q.na; ++a)
                     for (int b = 0; b < q.nb; ++b) {
+                        if (wab[a * 9 + b] == 0.0) continue;
                         const float* t = jb->lf + 3 * (q.ia[a] * P->N + q.jb[b]);
                         for (int c = 0; c < 3; ++c) out[c] += wab[a * 9 + b] * (double)t[c];
                     }
@@ -813,14 +816,10 @@ void orc_lookup_adjoint(const orc_params* prm, const orc_camera* cams, int32_t W
         query_pixel(prm, &cams[px[0]], W, H, K, px[1], px[2], &q);
         if (!q.ok) continue;
         double wab[81];
-        if (K == 1) {
-            double* t = d_lf + 3 * (q.ia[0] * prm->N + q.jb[0]);
-            for (int c = 0; c < 3; ++c) t[c] += dimg[3 * p + c];
-            continue;
-        }
         if (!pair_weights(prm, K, &q, wab)) continue;
         for (int a = 0; a < q.na; ++a)
             for (int b = 0; b < q.nb; ++b) {
+                if (wab[a * 9 + b] == 0.0) continue;
                 double* t = d_lf + 3 * (q.ia[a] * prm->N + q.jb[b]);
                 for (int c = 0; c < 3; ++c) t[c] += wab[a * 9 + b] * dimg[3 * p + c];
             }

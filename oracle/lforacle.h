@@ -58,6 +58,9 @@ typedef struct {
     double majorant;        /* <= 0: 1.25 * scale * max alpha of the sampling medium */
     uint64_t seed;
     int32_t jitter;         /* 1: jitter ray origins on the disk of area 4 pi R^2 / M */
+    int64_t origin_rows;    /* origins i < origin_rows are stored (0: all M); the
+                               light field is [origin_rows][N][3] (Sec. 3 keeps the
+                               upper hemisphere, origin_rows = M / 2) */
 } orc_params;
 
 typedef struct {
@@ -151,13 +154,15 @@ void orc_gradient(const orc_volume* vol, const orc_medium* med,
  * cams[] at W x H: RGB into rgb[3p..], nearest (i*, j*) into nn[2p..] (-1 on
  * miss), and the smallest decision margin into margin[4p..]: [tangent
  * test, nearest gap, zone, K-th gap] (min over both hit points).
- * lf is the light field as FP32 [M][N][3]. */
+ * lf is the light field as FP32 [rows][N][3], rows = origin_rows or M;
+ * neighbours i >= rows are not stored and carry weight 0 (a pixel left with
+ * none is 0, as is a K = 1 pixel whose nearest origin is not stored). */
 void orc_lookup(const float* lf, const orc_params* prm, const orc_camera* cams,
                 int32_t W, int32_t H, int32_t K, const int32_t* pix, int64_t npx,
                 double* rgb, int64_t* nn, double* margin, int32_t nthreads);
 
 /* Transpose of orc_lookup: d_lf[a][b][c] += weight(a,b) * dimg[p][c] for the
- * listed pixels; d_lf is FP64 [M][N][3], accumulated (not cleared). */
+ * listed pixels; d_lf is FP64 [rows][N][3], accumulated (not cleared). */
 void orc_lookup_adjoint(const orc_params* prm, const orc_camera* cams,
                         int32_t W, int32_t H, int32_t K, const int32_t* pix,
                         int64_t npx, const double* dimg, double* d_lf);

@@ -47,7 +47,8 @@ class _Light(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("M", C.c_int64), ("N", C.c_int64), ("center", C.c_double * 3), ("radius", C.c_double),
                 ("spp", C.c_int32), ("max_bounces", C.c_int32), ("g", C.c_double),
-                ("majorant", C.c_double), ("seed", C.c_uint64), ("jitter", C.c_int32)]
+                ("majorant", C.c_double), ("seed", C.c_uint64), ("jitter", C.c_int32),
+                ("origin_rows", C.c_int64)]
 
 
 class _Camera(C.Structure):
@@ -149,7 +150,14 @@ def _params(p):
     s.majorant = p.majorant
     s.seed = p.seed
     s.jitter = p.jitter
+    s.origin_rows = getattr(p, "origin_rows", 0)
     return s
+
+
+def stored_rows(p) -> int:
+    """Rows of origins the light field stores (origin_rows, 0 meaning M)."""
+    r = getattr(p, "origin_rows", 0)
+    return r if r > 0 else p.M
 
 
 def _cams(cams):
@@ -266,7 +274,7 @@ def gradient(scene, rays, adj, nthreads=None):
 
 def lookup(lf, params, cams, width, height, K, pix, nthreads=None):
     """RGB [npx,3], nearest (i,j) [npx,2], margins [npx,4] of the listed pixels
-    pix = [(view, x, y), ...] over the FP32 light field lf [M*N*3]."""
+    pix = [(view, x, y), ...] over the FP32 light field lf [rows*N*3]."""
     lf = np.ascontiguousarray(lf, dtype=np.float32).reshape(-1)
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
     n = pix.shape[0]
@@ -281,12 +289,12 @@ def lookup(lf, params, cams, width, height, K, pix, nthreads=None):
 
 
 def lookup_adjoint(params, cams, width, height, K, pix, dimg) -> np.ndarray:
-    """FP64 d_lf [M*N*3] = transpose of lookup applied to dimg [npx,3]."""
+    """FP64 d_lf [rows*N*3] = transpose of lookup applied to dimg [npx,3]."""
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
     dimg = np.ascontiguousarray(dimg, dtype=np.float64).reshape(-1, 3)
     p = _params(params)
     cs = _cams(cams)
-    d = np.zeros(params.M * params.N * 3)
+    d = np.zeros(stored_rows(params) * params.N * 3)
     lib().orc_lookup_adjoint(C.byref(p), cs, width, height, K, _ptr(pix), pix.shape[0], _ptr(dimg), _ptr(d))
     return d
 

@@ -63,7 +63,7 @@ class _Light(C.Structure):
 class _GenParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("center", C.c_float * 3), ("radius", C.c_float),
                 ("spp", C.c_int32), ("max_bounces", C.c_int32), ("hg_g", C.c_float), ("majorant", C.c_float),
-                ("seed", C.c_uint64), ("jitter", C.c_int32), ("reserved", C.c_int32),
+                ("seed", C.c_uint64), ("jitter", C.c_int32), ("origin_rows", C.c_int32),
                 ("row_begin", C.c_int64), ("row_end", C.c_int64), ("stats", C.c_void_p)]
 
 
@@ -189,6 +189,11 @@ class GenParams:
     jitter: int = 1
     row_begin: int = 0
     row_end: int = 0
+    origin_rows: int = 0                     # 0: all M origins; M // 2: upper hemisphere
+
+    @property
+    def rows(self) -> int:
+        return self.origin_rows if self.origin_rows > 0 else self.M
 
     def c(self, stats: Optional[torch.Tensor] = None) -> _GenParams:
         s = _GenParams()
@@ -199,6 +204,7 @@ class GenParams:
         s.hg_g, s.majorant = self.g, self.majorant
         s.seed = self.seed
         s.jitter = self.jitter
+        s.origin_rows = self.origin_rows
         s.row_begin, s.row_end = self.row_begin, self.row_end
         s.stats = _ptr(stats).value if stats is not None else None
         return s
@@ -239,7 +245,8 @@ def device_scene(scene, device="cuda"):
     light = Light(int(l.kind), l.dir, l.corner, l.e1, l.e2, l.radiance, l.env)
     p = scene.params
     prm = GenParams(int(p.M), int(p.N), tuple(p.center), float(p.radius), int(p.spp), int(p.max_bounces),
-                    float(p.g), float(p.majorant), int(p.seed), int(p.jitter))
+                    float(p.g), float(p.majorant), int(p.seed), int(p.jitter),
+                    origin_rows=int(getattr(p, "origin_rows", 0)))
     cams = [Camera(c.eye, c.target, c.up, c.vfov) for c in getattr(scene, "cams", [])]
     return vol, med, light, prm, cams
 
@@ -269,10 +276,11 @@ def _workspace(fn, *args) -> torch.Tensor:
 def generate(vol: Volume, med: Medium, light: Light, prm: GenParams, dtype: str = "f32",
              sample: Optional[Medium] = None, out: Optional[torch.Tensor] = None,
              stats: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """lf_generate: light field [M, N, 3] of `dtype` ('f32', 'f16', 'bf16')."""
+    """lf_generate: light field [rows, N, 3] of `dtype` ('f32', 'f16', 'bf16'),
+    rows = prm.origin_rows or M."""
     dt = DTYPES[dtype]
     if out is None:
-        out = torch.empty((prm.M, prm.N, 3), dtype=_TORCH_DTYPE[dt], device=vol.data.device)
+        out = torch.empty((prm.rows, prm.N, 3), dtype=_TORCH_DTYPE[dt], device=vol.data.device)
     L = library()
     v, m, l, p = vol.c(), med.c(), light.c(), prm.c(stats)
     s = sample.c() if sample is not None else None
@@ -313,11 +321,11 @@ def lookup(lf: torch.Tensor, prm: GenParams, cams: Sequence[Camera], width: int,
 
 def lookup_adjoint(dimg: torch.Tensor, prm: GenParams, cams: Sequence[Camera], K: int = 5,
                    d_lf: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """lf_lookup adjoint: d_lf [M, N, 3] (float32) += transpose applied to dimg."""
+    """lf_lookup adjoint: d_lf [rows, N, 3] (float32) += transpose applied to dimg."""
     dimg = dimg.contiguous().float()
     V, H, W, _ = dimg.shape
     if d_lf is None:
-        d_lf = torch.zeros((prm.M, prm.N, 3), dtype=torch.float32, device=dimg.device)
+        d_lf = torch.zeros((prm.rows, prm.N, 3), dtype=torch.float32, device=dimg.device)
     p = prm.c()
     cs = _cams(cams)
     _check(library().lf_lookup(None, 0, C.byref(p), cs, V, W, H, K, 1, _ptr(dimg), _ptr(d_lf), None,

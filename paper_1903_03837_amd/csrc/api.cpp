@@ -43,8 +43,10 @@ size_t brick4_bytes(const lf_volume* v) {
 // lf_generate workspace: majorant (offset 0), 8 tile counters (offset 64),
 // spatial order of the generated origin rows (offset 256), spatial order of
 // the directions, then the brick copy of the volume.
+long long stored_rows(const lf_gen_params* p) { return p->origin_rows > 0 ? p->origin_rows : p->M; }
+
 size_t gen_order_bytes(const lf_gen_params* p) {
-    const long long re = p->row_end <= 0 ? p->M : p->row_end;
+    const long long re = p->row_end <= 0 ? stored_rows(p) : p->row_end;
     const size_t rows = (size_t)(re - p->row_begin);
     return 256 + align256(4 * rows) + align256(4 * (size_t)p->N);
 }
@@ -57,14 +59,16 @@ int check_params(const lf_gen_params* p, bool need_rays) {
         return fail(LF_E_RANGE, "M*N must be < 2^32");
     if (!(p->radius > 0.0f) || !std::isfinite(p->radius)) return fail(LF_E_ARG, "radius must be > 0");
     if (!finite3(p->center)) return fail(LF_E_ARG, "center must be finite");
+    if (p->origin_rows < 0 || p->origin_rows > p->M) return fail(LF_E_ARG, "origin_rows must be in [0, M]");
     if (!need_rays) return LF_OK;
     if (p->spp < 1) return fail(LF_E_ARG, "spp must be >= 1");
     if (p->max_bounces < 1 || p->max_bounces > 65535) return fail(LF_E_ARG, "max_bounces must be in [1, 65535]");
     if (!(std::fabs(p->hg_g) < 1.0f)) return fail(LF_E_ARG, "|hg_g| must be < 1");
     if (!std::isfinite(p->majorant)) return fail(LF_E_ARG, "majorant must be finite");
-    const long long re = p->row_end <= 0 ? p->M : p->row_end;
-    if (p->row_begin < 0 || p->row_begin > re || re > p->M)
-        return fail(LF_E_ARG, "row range [%lld, %lld) outside [0, %d)", (long long)p->row_begin, re, p->M);
+    const long long rows = p->origin_rows > 0 ? p->origin_rows : p->M;
+    const long long re = p->row_end <= 0 ? rows : p->row_end;
+    if (p->row_begin < 0 || p->row_begin > re || re > rows)
+        return fail(LF_E_ARG, "row range [%lld, %lld) outside [0, %lld)", (long long)p->row_begin, re, rows);
     return LF_OK;
 }
 
@@ -177,7 +181,7 @@ void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, cons
     T.jitter = p->jitter != 0;
     T.jit_rad = (float)(2.0 * p->radius / std::sqrt((double)p->M));
     T.row_begin = (int32_t)p->row_begin;
-    T.row_end = (int32_t)(p->row_end <= 0 ? p->M : p->row_end);
+    T.row_end = (int32_t)(p->row_end <= 0 ? stored_rows(p) : p->row_end);
     T.stats = (unsigned long long*)p->stats;
 }
 
@@ -273,7 +277,7 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     if (!d_lf || !d_lut || !d_scale) return fail(LF_E_ARG, "d_lf, d_lut and d_scale must be non-NULL");
     // majorant, counters, spatial orders, list of rays with a nonzero adjoint,
     // then the brick copy of the volume
-    const long long re = params->row_end <= 0 ? params->M : params->row_end;
+    const long long re = params->row_end <= 0 ? stored_rows(params) : params->row_end;
     const size_t list_bytes = align256(4 * (size_t)(re - params->row_begin) * (size_t)params->N);
     const size_t need = gen_order_bytes(params) + list_bytes + brick4_bytes(vol);
     r = check_workspace(ws, ws_bytes, need);
@@ -343,6 +347,7 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
     L.K = K;
     L.dtype = dtype;
     L.degenerate = params->M == params->N;
+    L.orows = (int32_t)stored_rows(params);
     L.thr = (float)(1e-6 * R * R);
     L.lf = lf;
     L.img = img;

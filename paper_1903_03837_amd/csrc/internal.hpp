@@ -24,6 +24,7 @@ struct LookupParams {
     int32_t W, H, K;
     int32_t nviews, view0;
     int32_t dtype, degenerate;
+    int32_t orows;          // stored origin rows: neighbours i >= orows are uncovered
     float thr;              // tangent threshold 1e-6 R^2
     const void* lf;
     float* img;

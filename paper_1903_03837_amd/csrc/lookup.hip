@@ -122,13 +122,14 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
             const float* g = P.img + 3 * pix;
             gi = mk3(g[0], g[1], g[2]);
             if constexpr (KMAX == 1) {
-                wa[0] = wb[0] = 1.0f;
+                wa[0] = ia[0] < P.orows ? 1.0f : 0.0f;
+                wb[0] = 1.0f;
                 inv = 1.0f;
             } else {
                 float wsum = 0.0f;
 #pragma unroll
                 for (int a = 0; a < KMAX; ++a) {
-                    wa[a] = ia[a] >= 0 ? tent_weight(da[a], P.inv_rM) : 0.0f;
+                    wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight(da[a], P.inv_rM) : 0.0f;
                     wb[a] = jb[a] >= 0 ? tent_weight(db[a], P.inv_rN) : 0.0f;
                 }
 #pragma unroll
@@ -151,7 +152,7 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
             // nearest sampling (K = 1) copies the texel even when i == j
             const bool bad = KMAX > 1 && P.degenerate && ia[a] == jb[c];
             const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
-            const bool pend = live && w != 0.0f && ia[a] >= 0 && jb[c] >= 0;
+            const bool pend = live && w != 0.0f && ia[a] >= 0 && ia[a] < P.orows && jb[c] >= 0;
             const uint64_t key = (uint64_t)max(ia[a], 0) * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
             wave_scatter_add(P.d_lf, pend, key, gi * w);
         }
@@ -215,9 +216,10 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
     }
 
     if constexpr (KMAX == 1) {
-        const uint64_t t = (uint64_t)ia[0] * (uint64_t)P.N + (uint64_t)jb[0];
+        const bool covered = ia[0] < P.orows;
+        const uint64_t t = (uint64_t)(covered ? ia[0] : 0) * (uint64_t)P.N + (uint64_t)jb[0];
         if constexpr (MODE == 0) {
-            const f3 c = load_texel<DT>(P.lf, t);
+            const f3 c = covered ? load_texel<DT>(P.lf, t) : mk3(0.0f, 0.0f, 0.0f);
             float* o = P.img + 3 * pix;
             o[0] = c.x;
             o[1] = c.y;
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
     float wa[KMAX], wb[KMAX];
 #pragma unroll
     for (int a = 0; a < KMAX; ++a) {
-        wa[a] = ia[a] >= 0 ? tent_weight(da[a], P.inv_rM) : 0.0f;
+        wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight(da[a], P.inv_rM) : 0.0f;
         wb[a] = jb[a] >= 0 ? tent_weight(db[a], P.inv_rN) : 0.0f;
     }
     float wsum = 0.0f;
@@ -251,7 +253,8 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
                     const bool bad = P.degenerate && ia[a] == jb[c];
                     const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
                     // unconditional, in-range gathers so all KMAX^2 loads issue together
-                    const uint64_t t = (uint64_t)max(ia[a], 0) * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
+                    const int ai = (ia[a] >= 0 && ia[a] < P.orows) ? ia[a] : 0;
+                    const uint64_t t = (uint64_t)ai * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
                     acc = fma3(load_texel<DT>(P.lf, t), w, acc);
                 }
         }

@@ -334,6 +334,85 @@ def test_lookup_adjoint(lp, orc, M, N, K):
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
+# ------------------------------------------------- upper-hemisphere origins
+def test_generate_stored_rows(lp, orc):
+    """origin_rows = M/2 writes the first half of the full field, bit for bit,
+    as a [M/2][N][3] array; row slabs inside it split the same work."""
+    sc = S.config(1, M=96, N=80, spp=4)
+    full = gpu_field(lp, sc).reshape(96, 80, 3)
+    half_sc = sc.with_params(origin_rows=48)
+    vol, med, light, prm, _ = lp.device_scene(half_sc)
+    assert prm.rows == 48
+    lf = lp.generate(vol, med, light, prm)
+    assert tuple(lf.shape) == (48, 80, 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(lf.cpu().numpy().astype(np.float64), full[:48])
+    slab = torch.full_like(lf, -1.0)
+    for r0, r1 in ((0, 17), (17, 48)):
+        lp.generate(vol, med, light, dataclasses.replace(prm, row_begin=r0, row_end=r1), out=slab)
+    assert torch.equal(slab, lf)
+    ks = np.arange(48 * 80)
+    ref = orc.generate(half_sc, ks)
+    assert rel_l1(lf.reshape(-1, 3).double().cpu().numpy(), ref) <= RAD_TOL
+    with pytest.raises(lp.LumiPathError):
+        lp.generate(vol, med, light, dataclasses.replace(prm, row_end=49), out=lf)
+
+
+def stored_rows_case(lp, orc, M, N, rows, K, dtype="f32", seed=5):
+    R = math.sqrt(3.0)
+    rng = np.random.default_rng(seed)
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    lf = torch.from_numpy(rng.uniform(0.0, 1.0, (rows, N, 3)).astype(np.float32)).to(tdt).cuda()
+    cams = S.seam_cameras(R)
+    W, H = 64, 48
+    prm = lp.GenParams(M=M, N=N, radius=R, origin_rows=rows)
+    img, nn = lp.lookup(lf, prm, [lp.Camera(c.eye, c.target, c.up, c.vfov) for c in cams], W, H, K=K,
+                        with_nn=True)
+    torch.cuda.synchronize()
+    pix = orc.all_pixels(len(cams), W, H)
+    flat = (pix[:, 0].astype(np.int64) * H + pix[:, 2]) * W + pix[:, 1]
+    lf_host = lf.float().cpu().numpy()
+    rgb, onn, mg = orc.lookup(lf_host, S.Params(M=M, N=N, radius=R, origin_rows=rows), cams, W, H, K, pix)
+    clear = (mg[:, 0] > 1e-4) & (mg[:, 1] > BAND) & (mg[:, 2] > 1e-3) & ((mg[:, 3] > BAND) | (K == 1))
+    return (img.reshape(-1, 3).cpu().numpy()[flat], nn.reshape(-1, 2).cpu().numpy()[flat], rgb, onn, clear,
+            lookup_tol(M, N, lf_host), cams, W, H)
+
+
+@pytest.mark.parametrize("M,N,K", [(300, 256, 1), (300, 256, 5), (256, 256, 5), (300, 256, 9)])
+def test_lookup_stored_rows(lp, orc, M, N, K):
+    rows = M // 2
+    g_img, g_nn, rgb, onn, clear, tol, _, _, _ = stored_rows_case(lp, orc, M, N, rows, K)
+    assert clear.mean() > 0.99
+    assert np.array_equal(g_nn[clear], onn[clear])
+    uncovered = clear & (onn[:, 0] >= 0) & np.all(rgb == 0.0, 1)
+    assert uncovered.sum() > 100        # the views see origins that are not stored
+    assert np.all(g_img[uncovered] == 0.0)
+    if K == 1:
+        assert np.array_equal(g_img[clear], rgb[clear])
+    check_pixels(g_img[clear], rgb[clear], tol)
+
+
+@pytest.mark.parametrize("K", [1, 5])
+def test_lookup_adjoint_stored_rows(lp, orc, K):
+    M, N, rows = 96, 80, 48
+    R = math.sqrt(3.0)
+    cams = S.seam_cameras(R)
+    V, W, H = len(cams), 40, 30
+    prm = lp.GenParams(M=M, N=N, radius=R, origin_rows=rows)
+    rng = np.random.default_rng(6)
+    dimg = rng.standard_normal((V, H, W, 3)).astype(np.float32)
+    d_lf = lp.lookup_adjoint(torch.from_numpy(dimg).cuda(), prm,
+                             [lp.Camera(c.eye, c.target, c.up, c.vfov) for c in cams], K)
+    torch.cuda.synchronize()
+    assert tuple(d_lf.shape) == (rows, N, 3)
+    pix = orc.all_pixels(V, W, H)
+    flat = (pix[:, 0].astype(np.int64) * H + pix[:, 2]) * W + pix[:, 1]
+    ref = orc.lookup_adjoint(S.Params(M=M, N=N, radius=R, origin_rows=rows), cams, W, H, K, pix,
+                             dimg.reshape(-1, 3)[flat].astype(np.float64))
+    got = d_lf.reshape(-1).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
 # ------------------------------------------------------------------ adjoint
 def grad_scene():
     sc = S.config(1, M=48, N=48, spp=6, max_bounces=3, g=0.3)

@@ -88,3 +88,63 @@ def test_view_margins_reported(orc):
     hit = nn[:, 0] >= 0
     assert np.all(mg[hit] > 0)
     assert np.all(mg[~hit][:, 1:] == 1e300)
+
+
+def test_upper_hemisphere_is_first_half(orc):
+    """z_i falls with i, so the origins with z > 0 are the first floor(M/2)
+    indices (Sec. 3 stores that half of P_o)."""
+    for M in (12288, 301, 2):
+        z = orc.sf_points(M)[:, 2]
+        assert np.all(np.diff(z) < 0)
+        assert np.all(z[: M // 2] > 0) and np.all(z[(M + 1) // 2:] < 0)
+
+
+@pytest.mark.parametrize("M,N", [(300, 128), (256, 256)])
+def test_stored_origin_rows_renormalise(orc, M, N):
+    """Lookup over the stored rows i < rows is the full-M lookup restricted to
+    those origins and renormalised: with ind(i) = [i < rows],
+    half(g) = full(g * ind) / full(ind) wherever full(ind) > 0, else 0."""
+    rows = M // 2
+    V, W, H = 3, 36, 28
+    rng = np.random.default_rng(11)
+    cams = S.seam_cameras(math.sqrt(3.0))
+    half = S.Params(M=M, N=N, origin_rows=rows)
+    full = S.Params(M=M, N=N)
+    pix = orc.all_pixels(V, W, H)
+    g = rng.uniform(0.1, 1.0, (M, N, 3)).astype(np.float32)
+    ind = np.zeros((M, N, 3), np.float32)
+    ind[:rows] = 1.0
+    gi = (g * ind).astype(np.float32)
+    for K in (1, 5, 9):
+        h, nn_h, _ = orc.lookup(g[:rows], half, cams, W, H, K, pix)
+        f_gi, nn_f, _ = orc.lookup(gi, full, cams, W, H, K, pix)
+        f_ind, _, _ = orc.lookup(ind, full, cams, W, H, K, pix)
+        assert np.array_equal(nn_h, nn_f)
+        cov = f_ind[:, 0] > 0
+        hit = nn_f[:, 0] >= 0
+        # the views see both hemispheres and, for K > 1, the seam between them
+        assert (hit & cov).sum() > 0.1 * hit.sum() and (hit & ~cov).sum() > 0.1 * hit.sum()
+        if K > 1:
+            assert ((f_ind[:, 0] > 0) & (f_ind[:, 0] < 1 - 1e-9)).sum() > 0
+        else:
+            assert np.array_equal(cov, hit & (nn_f[:, 0] < rows))
+        ref = f_gi[cov] / f_ind[cov]
+        assert np.abs(h[cov] - ref).max() <= 1e-12
+        assert np.all(h[~cov] == 0.0)
+
+
+def test_stored_origin_rows_adjoint_is_transpose(orc):
+    M, N, rows = 96, 80, 48
+    rng = np.random.default_rng(12)
+    cams = S.seam_cameras(math.sqrt(3.0))
+    prm = S.Params(M=M, N=N, origin_rows=rows)
+    lf = rng.standard_normal(rows * N * 3).astype(np.float32)
+    pix = orc.all_pixels(3, 20, 16)
+    for K in (1, 5):
+        img, _, _ = orc.lookup(lf, prm, cams, 20, 16, K, pix)
+        dimg = rng.standard_normal(img.shape)
+        dlf = orc.lookup_adjoint(prm, cams, 20, 16, K, pix, dimg)
+        assert dlf.shape == (rows * N * 3,)
+        a = float((img * dimg).sum())
+        b = float((lf.astype(np.float64) * dlf).sum())
+        assert abs(a - b) < 1e-12 * (abs(a) + abs(b))
