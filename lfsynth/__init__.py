@@ -67,6 +67,7 @@ class Params:
     max_bounces: int = 4
     g: float = 0.0
     majorant: float = 0.0     # <= 0: 1.25 * scale * max alpha
+    grid: int = 0             # majorant grid cells per axis (0: one global majorant)
     seed: int = 0
     jitter: int = 1
     origin_rows: int = 0      # 0: all M origins; M // 2: upper hemisphere only

@@ -296,6 +296,60 @@ double orc_majorant(const orc_medium* sample, const orc_params* prm) {
     return 1.25 * sample->scale * amax;
 }
 
+/* Majorant grid: see lforacle.h for the definition restated here step by
+ * step.  Integer floor division for the block bounds (exact on both signs). */
+static int64_t floor_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+void orc_majorant_grid(const orc_volume* vol, const orc_medium* sample, const orc_params* prm, double* out) {
+    const int64_t G = prm->grid;
+    const int64_t n[3] = {vol->nx, vol->ny, vol->nz};
+    const int32_t L = sample->lut_size;
+    const double floor_maj = orc_majorant(sample, prm) / 256.0;
+    for (int64_t cz = 0; cz < G; ++cz)
+        for (int64_t cy = 0; cy < G; ++cy)
+            for (int64_t cx = 0; cx < G; ++cx) {
+                const int64_t c[3] = {cx, cy, cz};
+                int64_t lo[3], hi[3];
+                for (int a = 0; a < 3; ++a) {
+                    /* floor(c n / G - 1/2) = floor((2 c n - G) / (2 G)) */
+                    lo[a] = floor_div(2 * c[a] * n[a] - G, 2 * G) - 1;
+                    hi[a] = floor_div(2 * (c[a] + 1) * n[a] - G, 2 * G) + 2;
+                    if (lo[a] < 0) lo[a] = 0;
+                    if (hi[a] > n[a] - 1) hi[a] = n[a] - 1;
+                }
+                double vlo = INFINITY, vhi = -INFINITY;
+                for (int64_t z = lo[2]; z <= hi[2]; ++z)
+                    for (int64_t y = lo[1]; y <= hi[1]; ++y)
+                        for (int64_t x = lo[0]; x <= hi[0]; ++x) {
+                            double v = voxel(vol, x, y, z);
+                            if (v < vlo) vlo = v;
+                            if (v > vhi) vhi = v;
+                        }
+                double ulo = clamp01((vlo - vol->vmin) / (vol->vmax - vol->vmin)) * (double)(L - 1);
+                double uhi = clamp01((vhi - vol->vmin) / (vol->vmax - vol->vmin)) * (double)(L - 1);
+                int64_t e0 = (int64_t)floor(ulo), e1 = (int64_t)floor(uhi);
+                if (e0 > L - 2) e0 = L - 2;
+                if (e1 > L - 2) e1 = L - 2;
+                e1 += 1;
+                double amax = 0.0;
+                for (int64_t e = e0; e <= e1; ++e)
+                    if ((double)sample->lut[4 * e + 3] > amax) amax = (double)sample->lut[4 * e + 3];
+                double m = 1.25 * sample->scale * amax;
+                out[(cz * G + cy) * G + cx] = m > floor_maj ? m : floor_maj;
+            }
+}
+
+void orc_sigma_at(const orc_volume* vol, const orc_medium* med, const double* pts, int64_t npts, double* out) {
+    for (int64_t p = 0; p < npts; ++p) {
+        tfsample t = classify(vol, med, sample_volume(vol, pts + 3 * p));
+        out[p] = med->scale * t.alpha;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry helpers                                                           */
 /* ------------------------------------------------------------------------ */
@@ -360,6 +414,8 @@ typedef struct {
     const orc_light* light;
     const orc_params* prm;
     double sigbar;
+    int32_t grid;     /* cells per axis of the majorant grid, 0: global sigbar */
+    double* maj;      /* [grid^3] cell majorants */
     int frozen;       /* sample medium differs from eval medium */
     int light_on;     /* light radiance not all zero */
     /* gradient accumulation (NULL in plain forward mode) */
@@ -399,12 +455,85 @@ static void contribute(tracer* tr, double L[3], const double C[3], int with_shad
     tr->g_scale += aC * (tr->s_scale + (with_shadow ? tr->sh_scale : 0.0));
 }
 
+/* Piecewise-constant majorant along a segment.  The segment [tn, tf) of
+ * x + t d is cut where it crosses the grid's interior cell planes; each piece
+ * carries the majorant of the cell that holds its midpoint.  Without a grid
+ * the segment is one piece with the global majorant. */
+typedef struct { double t0, t1, maj; } piece;
+#define MAX_PIECES (3 * 64 + 2)
+
+static int cmp_double(const void* a, const void* b) {
+    double x = *(const double*)a, y = *(const double*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int segment_pieces(const tracer* tr, const double x[3], const double d[3], double tn, double tf,
+                          piece* pc) {
+    if (tr->grid <= 0) {
+        pc[0].t0 = tn; pc[0].t1 = tf; pc[0].maj = tr->sigbar;
+        return 1;
+    }
+    const int64_t G = tr->grid;
+    const double* bmin = tr->vol->box_min;
+    const double* bmax = tr->vol->box_max;
+    double cut[MAX_PIECES];
+    int nc = 0;
+    cut[nc++] = tn;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) continue;
+        for (int64_t m = 1; m < G; ++m) {
+            double plane = bmin[a] + (bmax[a] - bmin[a]) * (double)m / (double)G;
+            double t = (plane - x[a]) / d[a];
+            if (t > tn && t < tf) cut[nc++] = t;
+        }
+    }
+    qsort(cut + 1, (size_t)(nc - 1), sizeof(double), cmp_double);
+    cut[nc++] = tf;
+    int np = 0;
+    for (int q = 0; q + 1 < nc; ++q) {
+        if (!(cut[q + 1] > cut[q])) continue;
+        double mid = 0.5 * (cut[q] + cut[q + 1]);
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            double u = (x[a] + mid * d[a] - bmin[a]) / (bmax[a] - bmin[a]) * (double)G;
+            int64_t ci = (int64_t)floor(u);
+            c[a] = ci < 0 ? 0 : (ci > G - 1 ? G - 1 : ci);
+        }
+        pc[np].t0 = cut[q];
+        pc[np].t1 = cut[q + 1];
+        pc[np].maj = tr->maj[(c[2] * G + c[1]) * G + c[0]];
+        ++np;
+    }
+    return np;
+}
+
+/* Next tentative point after t for the unit-rate exponential variate tau:
+ * tau is spent piece by piece at each piece's majorant (a zero-majorant
+ * piece spends none).  Returns 0 when the segment ends first; otherwise sets
+ * t and the majorant in force there. */
+static int next_tentative(const piece* pc, int np, double* t, double tau, double* maj) {
+    for (int p = 0; p < np; ++p) {
+        if (pc[p].t1 <= *t) continue;
+        double a = pc[p].t0 > *t ? pc[p].t0 : *t;
+        if (pc[p].maj > 0.0) {
+            double tc = a + tau / pc[p].maj;
+            if (tc < pc[p].t1) {
+                *t = tc;
+                *maj = pc[p].maj;
+                return 1;
+            }
+            tau -= pc[p].maj * (pc[p].t1 - a);
+        }
+    }
+    return 0;
+}
+
 static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t s, double L[3]) {
     const orc_params* P = tr->prm;
     const orc_light* lt = tr->light;
     const double* bmin = tr->vol->box_min;
     const double* bmax = tr->vol->box_max;
-    double sigbar = tr->sigbar;
+    double sigbar = tr->sigbar;   /* majorant in force at the current tentative point */
     double po[3], pd[3], dir[3], x[3];
     orc_sf_point(P->M, i, po);
     orc_sf_point(P->N, j, pd);
@@ -440,19 +569,21 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
         int real = 0;
         double y[3];
         tfsample te = {0, 0.0, 0.0, {0.0, 0.0, 0.0}};
-        if (hit && sigbar > 0.0) {
-            /* delta tracking: tentative collisions at rate sigbar; the n-th
-             * uses pair n (n+1 on the first segment, after the jitter pair):
-             * distance, then acceptance */
+        if (hit && tr->sigbar > 0.0) {
+            /* delta tracking: tentative collisions at the local majorant
+             * rate; the n-th uses pair n (n+1 on the first segment, after
+             * the jitter pair): distance variate tau = -ln(1 - u), then
+             * acceptance */
             ustream uf;
             us_init(&uf, P->seed, k, s, (uint32_t)b, P_FLIGHT);
             int64_t first = b == 0 ? 1 : 0;
+            piece pc[MAX_PIECES];
+            int np = segment_pieces(tr, x, dir, tn, tf, pc);
             double t = tn;
             for (int64_t pair = first;; ++pair) {
                 if (pair == MAX_PAIRS) return; /* cap reached: absorbed */
                 double ud = us_get(&uf, 2 * pair), ua = us_get(&uf, 2 * pair + 1);
-                t -= log(1.0 - ud) / sigbar;
-                if (t >= tf) break;
+                if (!next_tentative(pc, np, &t, -log(1.0 - ud), &sigbar)) break;
                 tr->stats[0] += 1.0;
                 for (int a = 0; a < 3; ++a) y[a] = x[a] + t * dir[a];
                 double raw = sample_volume(tr->vol, y);
@@ -524,12 +655,13 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
                 memset(tr->sh_alpha, 0, sizeof(double) * tr->eval->lut_size);
                 tr->sh_scale = 0.0;
             }
-            if (sigbar > 0.0) {
+            if (tr->sigbar > 0.0) {
                 double t = 0.0;
+                piece pc[MAX_PIECES];
+                int np = segment_pieces(tr, x, om, 0.0, tend, pc);
                 for (int64_t pair = 2;; ++pair) {
                     if (pair == MAX_PAIRS) { Tr = 0.0; break; } /* cap reached: blocked */
-                    t -= log(1.0 - us_get(&uv, 2 * pair)) / sigbar;
-                    if (t >= tend) break;
+                    if (!next_tentative(pc, np, &t, -log(1.0 - us_get(&uv, 2 * pair)), &sigbar)) break;
                     tr->stats[1] += 1.0;
                     double z[3];
                     for (int a = 0; a < 3; ++a) z[a] = x[a] + t * om[a];
@@ -577,6 +709,11 @@ static void tracer_setup(tracer* tr, const orc_volume* vol, const orc_medium* ev
     tr->light = light;
     tr->prm = prm;
     tr->sigbar = orc_majorant(tr->samp, prm);
+    tr->grid = prm->majorant > 0.0 ? 0 : prm->grid;
+    if (tr->grid > 0) {
+        tr->maj = (double*)malloc(sizeof(double) * (size_t)tr->grid * tr->grid * tr->grid);
+        orc_majorant_grid(vol, tr->samp, prm, tr->maj);
+    }
     tr->frozen = sample != NULL && sample != eval;
     tr->light_on = light->radiance[0] != 0.0 || light->radiance[1] != 0.0 || light->radiance[2] != 0.0;
 }
@@ -634,6 +771,7 @@ void orc_generate(const orc_volume* vol, const orc_medium* eval, const orc_mediu
         jobs[t].out = out;
     }
     run_jobs(jobs, nthreads);
+    for (int32_t t = 0; t < nthreads; ++t) free(jobs[t].tr.maj);
     if (stats) {
         for (int a = 0; a < 4; ++a) stats[a] = 0.0;
         for (int32_t t = 0; t < nthreads; ++t)
@@ -671,6 +809,7 @@ void orc_gradient(const orc_volume* vol, const orc_medium* med, const orc_light*
         free(jobs[t].tr.s_rgb);
         free(jobs[t].tr.sh_alpha);
         free(jobs[t].tr.g_lut);
+        free(jobs[t].tr.maj);
     }
     free(jobs);
 }

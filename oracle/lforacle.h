@@ -58,6 +58,8 @@ typedef struct {
     double majorant;        /* <= 0: 1.25 * scale * max alpha of the sampling medium */
     uint64_t seed;
     int32_t jitter;         /* 1: jitter ray origins on the disk of area 4 pi R^2 / M */
+    int32_t grid;           /* majorant grid: G cells per axis (0: one global
+                               majorant); ignored when majorant > 0 */
     int64_t origin_rows;    /* origins i < origin_rows are stored (0: all M); the
                                light field is [origin_rows][N][3] (Sec. 3 keeps the
                                upper hemisphere, origin_rows = M / 2) */
@@ -125,13 +127,36 @@ void orc_frame(const double n[3], double t1[3], double t2[3]);
 /* ---- Majorant: params majorant if > 0 else 1.25 * scale * max alpha ---- */
 double orc_majorant(const orc_medium* sample, const orc_params* prm);
 
+/* ---- Majorant grid (piecewise-constant majorant of delta and ratio
+ * tracking, as in PBRT's grid media) -------------------------------------
+ * G = prm->grid (1..64) splits the volume box into G^3 equal cells, x
+ * fastest.  Cell c must bound sigma_t of the sampling medium wherever the
+ * trilinear footprint of a point in it can reach, with one voxel to spare
+ * on each side: per axis, voxels floor(c n / G - 1/2) - 1 ..
+ * floor((c + 1) n / G - 1/2) + 2, clamped to the grid.  [lo, hi] is the raw
+ * range of that block, u(v) = clamp((v - vmin) / (vmax - vmin), 0, 1) (L-1),
+ * and the LUT entries min(floor u(lo), L-2) .. min(floor u(hi), L-2) + 1
+ * hold every alpha a point of the cell can take; the majorant is
+ * max(1.25 scale max alpha over them, orc_majorant / 256).  The floor keeps
+ * null collisions, and so the score of every LUT entry, possible in empty
+ * cells.  Pinned by brute-force sampling of sigma_t, a constant volume
+ * (closed form) and the floor in empty space. */
+void orc_majorant_grid(const orc_volume* vol, const orc_medium* sample, const orc_params* prm, double* out);
+
+/* sigma_t = scale * alpha of `med` at npts world points pts[3p..] (trilinear
+ * raw value, classification); exposed for the pins above. */
+void orc_sigma_at(const orc_volume* vol, const orc_medium* med, const double* pts, int64_t npts, double* out);
+
 /* ---- Light-field generation (Sec. 2, ray set R^K, origin jitter, path
  * tracer; volumetric reading) ---------------------------------------------
  * For each ray index k = i*N + j in rays[0..nrays) writes the mean radiance
  * over spp samples to out[3*r .. 3*r+2].  `sample` may equal `eval`; when it
  * differs, collisions are decided with `sample` and importance-weighted to
- * `eval` (frozen sampling).  Pinned by Beer-Lambert, white furnace, vacuum,
- * linearity and symmetry checks.  stats (may be NULL) receives
+ * `eval` (frozen sampling).  With prm->grid > 0 (and no fixed majorant)
+ * both trackings use the majorant grid above.  Pinned by Beer-Lambert,
+ * white furnace, vacuum, linearity and symmetry checks, and, for the grid,
+ * by quadrature of heterogeneous transmittance and agreement in expectation
+ * with the global majorant.  stats (may be NULL) receives
  * [tentative collisions of primary tracking, shadow steps, real collisions,
  * samples]. */
 void orc_generate(const orc_volume* vol, const orc_medium* eval,

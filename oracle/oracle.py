@@ -48,7 +48,7 @@ class _Params(C.Structure):
     _fields_ = [("M", C.c_int64), ("N", C.c_int64), ("center", C.c_double * 3), ("radius", C.c_double),
                 ("spp", C.c_int32), ("max_bounces", C.c_int32), ("g", C.c_double),
                 ("majorant", C.c_double), ("seed", C.c_uint64), ("jitter", C.c_int32),
-                ("origin_rows", C.c_int64)]
+                ("grid", C.c_int32), ("origin_rows", C.c_int64)]
 
 
 class _Camera(C.Structure):
@@ -87,6 +87,8 @@ def lib():
         L.orc_frame.argtypes = [P, P, P]
         L.orc_majorant.argtypes = [P, P]
         L.orc_majorant.restype = C.c_double
+        L.orc_majorant_grid.argtypes = [P, P, P, P]
+        L.orc_sigma_at.argtypes = [P, P, P, C.c_int64, P]
         L.orc_generate.argtypes = [P, P, P, P, P, P, C.c_int64, P, C.c_int32, P]
         L.orc_gradient.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, C.c_int32]
         L.orc_lookup.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64, P, P, P, C.c_int32]
@@ -150,6 +152,7 @@ def _params(p):
     s.majorant = p.majorant
     s.seed = p.seed
     s.jitter = p.jitter
+    s.grid = getattr(p, "grid", 0)
     s.origin_rows = getattr(p, "origin_rows", 0)
     return s
 
@@ -237,6 +240,31 @@ def majorant(medium, params) -> float:
     m = _med(medium, keep)
     p = _params(params)
     return lib().orc_majorant(C.byref(m), C.byref(p))
+
+
+def majorant_grid(volume, medium, params) -> np.ndarray:
+    """Cell majorants [G, G, G] (z, y, x) of the majorant grid, G = params.grid."""
+    keep = []
+    v = _vol(volume, keep)
+    m = _med(medium, keep)
+    p = _params(params)
+    G = int(params.grid)
+    if not 1 <= G <= 64:
+        raise ValueError("grid must be in [1, 64]")
+    out = np.zeros(G * G * G)
+    lib().orc_majorant_grid(C.byref(v), C.byref(m), C.byref(p), _ptr(out))
+    return out.reshape(G, G, G)
+
+
+def sigma_at(volume, medium, pts) -> np.ndarray:
+    """sigma_t of `medium` at world points pts [n, 3]."""
+    keep = []
+    v = _vol(volume, keep)
+    m = _med(medium, keep)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(len(pts))
+    lib().orc_sigma_at(C.byref(v), C.byref(m), _ptr(pts), len(pts), _ptr(out))
+    return out
 
 
 def generate(scene, rays, sample_medium=None, nthreads=None, stats=False):
