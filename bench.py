@@ -4,7 +4,7 @@
 One step = one pass of the whole path over the CT-like workload (256^3 u16
 phantom, M = N = 2048 spherical-Fibonacci points, 4.19M rays, 64 samples per
 ray, 8 bounces, HG g = 0.3, area light):
-  lf_points (SF table) -> lf_generate (FP32 light field) -> lf_lookup (32 views
+  lf_points (SF table) -> lf_generate (FP32 light field, 4^3 majorant grid) -> lf_lookup (32 views
   of 1920 x 1080, K = 5) -> L2 view loss gradient -> lf_lookup adjoint ->
   lf_generate_backward (d LUT, d density scale).
 `value` = M*N*spp path samples per second of the whole step.  One JSON line
@@ -29,6 +29,7 @@ OPS_SHADOW = 90         # ratio-tracking step: 1/4 Philox, log, trilinear fetch,
 OPS_REAL = 270          # scatter vertex: albedo, Philox block, light sample, phase eval/sample, clips
 OPS_SAMPLE = 140        # jitter (Philox block, sqrt, sincos, frame), first clip, escape, accumulate
 OPS_RAY = 80            # two SF points (FP64 frac), direction, store
+OPS_CELL = 16           # majorant-grid step: cell majorant read, 3-way min, spend/compare, advance
 PEAK_OPS = 256 * 4 * 16 * 2.4e9   # 32-bit lane ops per second: CUs x SIMDs x lanes x clock
 PEAK_HBM = 8.0e12
 
@@ -121,13 +122,13 @@ def main():
     target = lp.lookup(lp.generate(vol, tmed, light, prm), prm, cams, W, H, K)
 
     # counts of the units of work (deterministic for the fixed stream)
-    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    stats = torch.zeros(5, dtype=torch.int64, device=dev)
     lp.generate(vol, med, light, prm, out=lf, stats=stats)
     torch.cuda.synchronize()
-    tent, shadow, real, samples = (int(x) for x in stats.cpu().numpy())
+    tent, shadow, real, samples, cells = (int(x) for x in stats.cpu().numpy())
     rays = M * N - (M if M == N else 0)
     alg_ops = (tent * OPS_TENTATIVE + shadow * OPS_SHADOW + real * OPS_REAL + samples * OPS_SAMPLE
-               + rays * OPS_RAY)
+               + rays * OPS_RAY + cells * OPS_CELL)
 
     stream = torch.cuda.current_stream()
     nev = 7
@@ -204,10 +205,10 @@ def main():
         "data": "synthetic (seeded CT-like phantom, transfer function, area light, cameras)",
         "config": {
             "workload": "CT-like phantom 256^3 u16 (12 nested ellipsoids), M=N=2048 SF points (4.19M rays), "
-                        "64 spp, 8 bounces, HG g=0.3, area light, FP32 light field; lookup of 32 views "
-                        "1920x1080 K=5; adjoint of an L2 view loss",
+                        "64 spp, 8 bounces, HG g=0.3, area light, 4^3 majorant grid, FP32 light field; lookup of "
+                        "32 views 1920x1080 K=5; adjoint of an L2 view loss",
             "M": M, "N": N, "spp": spp, "max_bounces": prm.max_bounces, "views": V, "width": W, "height": H,
-            "K": K, "volume": "256^3 u16 linear",
+            "K": K, "volume": "256^3 u16 linear", "majorant_grid": prm.grid,
         },
         "roofline": {
             "kernel": "gen_kernel (lf_generate)",
@@ -223,7 +224,7 @@ def main():
             "launch_ms": legs["generate"],
             "ops_per_launch": alg_ops,
             "units_per_launch": {"tentative_collisions": tent, "shadow_steps": shadow, "real_collisions": real,
-                                 "samples": samples, "rays": rays},
+                                 "samples": samples, "rays": rays, "majorant_cell_steps": cells},
         },
         "legs_ms": legs,
         "generate_samples_per_s": M * N * spp / gen_s,
@@ -233,6 +234,7 @@ def main():
         "fp16_vs_fp32_rel_err": err16,
         "bf16_vs_fp32_rel_err": errb16,
         "collisions_per_sample": tent / samples,
+        "cell_steps_per_sample": cells / samples,
         "kernel_hash": khash,
     }
     if not args.no_cpu_baseline:

@@ -99,11 +99,19 @@ typedef struct {
  * halving the texture); lookups whose front hit has no stored origin are
  * uncovered (pixel 0).
  * spp >= 1 samples, 1 <= max_bounces <= 65535 scatter vertices, |hg_g| < 1.
- * majorant <= 0 selects 1.25 * density_scale * max alpha of the sampling
- * medium.  Rows [row_begin, row_end) of i are generated (row_end <= 0:
- * origin_rows); results do not depend on this split.  stats: NULL or device
- * uint64[4] incremented by [tentative collisions, shadow-ray steps, real
- * collisions, path samples]. */
+ * majorant > 0 fixes one global majorant; otherwise it is 1.25 *
+ * density_scale * max alpha of the sampling medium, and majorant_grid = G in
+ * [1, 16] replaces it by a grid of G^3 cell majorants over the volume box
+ * (piecewise-constant majorant, as in PBRT's grid media): each cell bounds
+ * 1.25 sigma_t of the sampling medium over the voxels its points can reach
+ * (one voxel to spare), floored at 1/256 of the global majorant so that null
+ * collisions stay possible everywhere.  Tentative collisions then spend the
+ * exponential variate cell by cell; the random-number layout is unchanged.
+ * G = 0 keeps the global majorant.  Rows [row_begin, row_end) of i are
+ * generated (row_end <= 0: origin_rows); results do not depend on this
+ * split.  stats: NULL or device uint64[5] incremented by [tentative
+ * collisions, shadow-ray steps, real collisions, path samples, majorant-cell
+ * steps]. */
 typedef struct {
     int32_t M, N;
     float center[3];
@@ -111,6 +119,7 @@ typedef struct {
     int32_t spp, max_bounces;
     float hg_g;
     float majorant;
+    int32_t majorant_grid;  /* cells per axis of the majorant grid, 0 = global */
     uint64_t seed;
     int32_t jitter;
     int32_t origin_rows;    /* stored origin rows: 0 = M; M/2 keeps the upper hemisphere */
@@ -174,6 +183,14 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
 int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams,
               int32_t n_views, int32_t W, int32_t H, int32_t K, int32_t mode, float* img,
               float* d_lf, int32_t* nn_out, void* stream);
+
+/* Cell majorants of the majorant grid that lf_generate and
+ * lf_generate_backward track against (piecewise-constant majorant; the grid
+ * and its bound are defined with lf_gen_params): out (device float
+ * [G][G][G], x fastest, G = params->majorant_grid >= 1) for the medium
+ * `sample`.  params->majorant is not consulted.  Stream-ordered on `stream`. */
+int lf_majorant_grid(const lf_volume* vol, const lf_medium* sample, const lf_gen_params* params, float* out,
+                     void* stream);
 
 /* Adjoint of lf_generate (path-replay extension): given d_lf = d(loss)/d(Lhat)
  * (float32 [origin_rows][N][3]), overwrites d_lut (float32 [lut_size][4]) and d_scale

@@ -298,7 +298,10 @@ def _phantom(n: int, seed: int, nell: int, brick: int) -> Volume:
 def config(c: int, **over) -> Scene:
     """Workload c (1..5) at its full size.  Keyword overrides replace run
     parameters (M, N, spp, max_bounces, ...) or view settings (views, width,
-    height, K) so tests can run the same scene at smaller sizes."""
+    height, K) so tests can run the same scene at smaller sizes.  Every
+    workload tracks against a majorant grid, G^3 cells with G measured
+    fastest on MI355X for that workload (grid=0 selects the global
+    majorant)."""
     R = math.sqrt(3.0)
     views = over.pop("views", None)
     width = over.pop("width", None)
@@ -308,25 +311,25 @@ def config(c: int, **over) -> Scene:
     if c == 1:
         vol = _blob(vol_n or 64, 1001, U8)
         lt = directional_light(3001)
-        prm = Params(M=256, N=256, radius=R, spp=16, max_bounces=4, g=0.0, seed=4001)
+        prm = Params(M=256, N=256, radius=R, spp=16, max_bounces=4, g=0.0, seed=4001, grid=4)
         nv, w, h = 4, 64, 48
     elif c == 2:
         vol = _phantom(vol_n or 256, 1002, 12, 0)
         lt = area_light(3002, R)
-        prm = Params(M=2048, N=2048, radius=R, spp=64, max_bounces=8, g=0.3, seed=4002)
+        prm = Params(M=2048, N=2048, radius=R, spp=64, max_bounces=8, g=0.3, seed=4002, grid=4)
         nv, w, h = 32, 1920, 1080
     elif c in (3, 4):
         vol = _phantom(vol_n or 512, 1003, 40, 8)
         lt = area_light(3003 if c == 3 else 3004, R)
         if c == 3:
-            prm = Params(M=8192, N=8192, radius=R, spp=128, max_bounces=8, g=0.3, seed=4003)
+            prm = Params(M=8192, N=8192, radius=R, spp=128, max_bounces=8, g=0.3, seed=4003, grid=8)
         else:
-            prm = Params(M=32768, N=32768, radius=R, spp=16, max_bounces=8, g=0.3, seed=4004)
+            prm = Params(M=32768, N=32768, radius=R, spp=16, max_bounces=8, g=0.3, seed=4004, grid=8)
         nv, w, h = 4, 512, 512
     elif c == 5:
         vol = _blob(vol_n or 128, 1005, F32)
         lt = directional_light(3005)
-        prm = Params(M=1024, N=1024, radius=R, spp=32, max_bounces=4, g=0.0, seed=4005)
+        prm = Params(M=1024, N=1024, radius=R, spp=32, max_bounces=4, g=0.0, seed=4005, grid=5)
         nv, w, h = 16, 512, 512
     else:
         raise ValueError(f"unknown workload {c}")

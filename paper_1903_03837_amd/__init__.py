@@ -25,7 +25,7 @@ import torch
 
 __all__ = [
     "LumiPathError", "Volume", "Medium", "Light", "GenParams", "Camera", "library", "library_path",
-    "points", "generate", "generate_backward", "lookup", "lookup_adjoint", "LightFieldFn", "LookupFn",
+    "points", "generate", "generate_backward", "lookup", "majorant_grid", "lookup_adjoint", "LightFieldFn", "LookupFn",
     "device_scene", "DTYPES",
 ]
 
@@ -63,6 +63,7 @@ class _Light(C.Structure):
 class _GenParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("center", C.c_float * 3), ("radius", C.c_float),
                 ("spp", C.c_int32), ("max_bounces", C.c_int32), ("hg_g", C.c_float), ("majorant", C.c_float),
+                ("majorant_grid", C.c_int32),
                 ("seed", C.c_uint64), ("jitter", C.c_int32), ("origin_rows", C.c_int32),
                 ("row_begin", C.c_int64), ("row_end", C.c_int64), ("stats", C.c_void_p)]
 
@@ -94,7 +95,8 @@ def library():
         L.lf_generate_backward.argtypes = [P, P, P, P, P, P, P, P, C.POINTER(C.c_size_t), P]
         L.lf_lookup.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 P, P, P, P]
-        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup):
+        L.lf_majorant_grid.argtypes = [P, P, P, P, P]
+        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_majorant_grid):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -103,6 +105,17 @@ def library():
 def _check(code: int):
     if code != 0:
         raise LumiPathError(code, library().lf_last_error().decode())
+
+
+def _need(t: torch.Tensor, numel: int, dtypes, name: str):
+    """The C ABI takes plain device pointers: check here that a buffer holds
+    what the call will read or write."""
+    if not isinstance(dtypes, tuple):
+        dtypes = (dtypes,)
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype} not in {dtypes}")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, {numel} needed")
 
 
 def _stream() -> C.c_void_p:
@@ -190,6 +203,7 @@ class GenParams:
     row_begin: int = 0
     row_end: int = 0
     origin_rows: int = 0                     # 0: all M origins; M // 2: upper hemisphere
+    grid: int = 0                            # majorant grid cells per axis (0: one global majorant)
 
     @property
     def rows(self) -> int:
@@ -202,10 +216,13 @@ class GenParams:
         s.radius = self.radius
         s.spp, s.max_bounces = self.spp, self.max_bounces
         s.hg_g, s.majorant = self.g, self.majorant
+        s.majorant_grid = self.grid
         s.seed = self.seed
         s.jitter = self.jitter
         s.origin_rows = self.origin_rows
         s.row_begin, s.row_end = self.row_begin, self.row_end
+        if stats is not None:
+            _need(stats, 5, torch.int64, "stats")
         s.stats = _ptr(stats).value if stats is not None else None
         return s
 
@@ -246,7 +263,7 @@ def device_scene(scene, device="cuda"):
     p = scene.params
     prm = GenParams(int(p.M), int(p.N), tuple(p.center), float(p.radius), int(p.spp), int(p.max_bounces),
                     float(p.g), float(p.majorant), int(p.seed), int(p.jitter),
-                    origin_rows=int(getattr(p, "origin_rows", 0)))
+                    origin_rows=int(getattr(p, "origin_rows", 0)), grid=int(getattr(p, "grid", 0)))
     cams = [Camera(c.eye, c.target, c.up, c.vfov) for c in getattr(scene, "cams", [])]
     return vol, med, light, prm, cams
 
@@ -281,6 +298,7 @@ def generate(vol: Volume, med: Medium, light: Light, prm: GenParams, dtype: str 
     dt = DTYPES[dtype]
     if out is None:
         out = torch.empty((prm.rows, prm.N, 3), dtype=_TORCH_DTYPE[dt], device=vol.data.device)
+    _need(out, prm.rows * prm.N * 3, _TORCH_DTYPE[dt], "out")
     L = library()
     v, m, l, p = vol.c(), med.c(), light.c(), prm.c(stats)
     s = sample.c() if sample is not None else None
@@ -291,9 +309,21 @@ def generate(vol: Volume, med: Medium, light: Light, prm: GenParams, dtype: str 
     return out
 
 
+def majorant_grid(vol: Volume, med: Medium, prm: GenParams) -> torch.Tensor:
+    """lf_majorant_grid: cell majorants [G, G, G] (z, y, x) for G = prm.grid."""
+    G = prm.grid
+    if G < 1:
+        raise ValueError("prm.grid must be >= 1")
+    out = torch.empty((G, G, G), dtype=torch.float32, device=med.lut.device)
+    v, m, p = vol.c(), med.c(), prm.c()
+    _check(library().lf_majorant_grid(C.byref(v), C.byref(m), C.byref(p), _ptr(out), _stream()))
+    return out
+
+
 def generate_backward(vol: Volume, med: Medium, light: Light, prm: GenParams, d_lf: torch.Tensor):
     """lf_generate_backward: (d_lut [L,4], d_scale [1]) for d(loss)/d(Lhat)."""
     d_lf = d_lf.contiguous().float()
+    _need(d_lf, prm.rows * prm.N * 3, torch.float32, "d_lf")
     d_lut = torch.empty_like(med.lut)
     d_scale = torch.empty(1, dtype=torch.float32, device=med.lut.device)
     L = library()
@@ -309,8 +339,10 @@ def lookup(lf: torch.Tensor, prm: GenParams, cams: Sequence[Camera], width: int,
     """lf_lookup forward: images [V, H, W, 3] (and nearest (i, j) [V, H, W, 2])."""
     dt = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}[lf.dtype]
     V = len(cams)
+    _need(lf, prm.rows * prm.N * 3, lf.dtype, "lf")
     if img is None:
         img = torch.empty((V, height, width, 3), dtype=torch.float32, device=lf.device)
+    _need(img, V * height * width * 3, torch.float32, "img")
     nn = torch.empty((V, height, width, 2), dtype=torch.int32, device=lf.device) if with_nn else None
     p = prm.c()
     cs = _cams(cams)
@@ -326,6 +358,7 @@ def lookup_adjoint(dimg: torch.Tensor, prm: GenParams, cams: Sequence[Camera], K
     V, H, W, _ = dimg.shape
     if d_lf is None:
         d_lf = torch.zeros((prm.rows, prm.N, 3), dtype=torch.float32, device=dimg.device)
+    _need(d_lf, prm.rows * prm.N * 3, torch.float32, "d_lf")
     p = prm.c()
     cs = _cams(cams)
     _check(library().lf_lookup(None, 0, C.byref(p), cs, V, W, H, K, 1, _ptr(dimg), _ptr(d_lf), None,

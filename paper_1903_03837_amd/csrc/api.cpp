@@ -42,13 +42,22 @@ size_t brick4_bytes(const lf_volume* v) {
 
 // lf_generate workspace: majorant (offset 0), 8 tile counters (offset 64),
 // spatial order of the generated origin rows (offset 256), spatial order of
-// the directions, then the brick copy of the volume.
+// the directions, the cell majorants of the grid (when used), then the brick
+// copy of the volume.
 long long stored_rows(const lf_gen_params* p) { return p->origin_rows > 0 ? p->origin_rows : p->M; }
 
-size_t gen_order_bytes(const lf_gen_params* p) {
+// Cells per axis of the majorant grid in use (0: the global majorant).
+int grid_cells(const lf_gen_params* p) { return p->majorant > 0.0f ? 0 : p->majorant_grid; }
+
+size_t gen_perm_bytes(const lf_gen_params* p) {
     const long long re = p->row_end <= 0 ? stored_rows(p) : p->row_end;
     const size_t rows = (size_t)(re - p->row_begin);
     return 256 + align256(4 * rows) + align256(4 * (size_t)p->N);
+}
+
+size_t gen_order_bytes(const lf_gen_params* p) {
+    const size_t G = (size_t)grid_cells(p);
+    return gen_perm_bytes(p) + align256(4 * G * G * G);
 }
 
 int check_params(const lf_gen_params* p, bool need_rays) {
@@ -65,6 +74,8 @@ int check_params(const lf_gen_params* p, bool need_rays) {
     if (p->max_bounces < 1 || p->max_bounces > 65535) return fail(LF_E_ARG, "max_bounces must be in [1, 65535]");
     if (!(std::fabs(p->hg_g) < 1.0f)) return fail(LF_E_ARG, "|hg_g| must be < 1");
     if (!std::isfinite(p->majorant)) return fail(LF_E_ARG, "majorant must be finite");
+    if (p->majorant_grid < 0 || p->majorant_grid > 16)
+        return fail(LF_E_ARG, "majorant_grid must be in [0, 16] (got %d)", p->majorant_grid);
     const long long rows = p->origin_rows > 0 ? p->origin_rows : p->M;
     const long long re = p->row_end <= 0 ? rows : p->row_end;
     if (p->row_begin < 0 || p->row_begin > re || re > rows)
@@ -183,6 +194,39 @@ void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, cons
     T.row_begin = (int32_t)p->row_begin;
     T.row_end = (int32_t)(p->row_end <= 0 ? stored_rows(p) : p->row_end);
     T.stats = (unsigned long long*)p->stats;
+    const int G = grid_cells(p);
+    T.grid_n = G > 0 ? G : 1;
+    for (int a = 0; a < 3; ++a) {
+        const double ext = (double)v->box_max[a] - (double)v->box_min[a];
+        T.gcell[a] = (float)(T.grid_n / ext);
+        T.gcw[a] = (float)(ext / T.grid_n);
+    }
+    T.nz = v->nz;
+}
+
+// Majorant set-up shared by both entry points: the global majorant, the tile
+// counters and spatial orders, then (with a grid) the cell majorants; without
+// a grid the one cell's majorant is the global one.
+hipError_t setup_tracking(lp::TraceParams& T, const lf_volume* vol, const lf_medium* sm, const lf_gen_params* p,
+                          char* w, hipStream_t s) {
+    float* sig = (float*)w;
+    unsigned int* ctr = (unsigned int*)(w + 64);
+    int32_t* perm_o = (int32_t*)(w + 256);
+    int32_t* perm_d = (int32_t*)(w + 256 + align256(4 * (size_t)(T.row_end - T.row_begin)));
+    T.sigbar = sig;
+    T.tile_ctr = ctr;
+    T.perm_o = perm_o;
+    T.perm_d = perm_d;
+    T.maj = sig;
+    hipError_t e = lp::launch_wave_setup(T, sm->lut, sm->lut_size, sm->density_scale, p->majorant, sig, ctr,
+                                         perm_o, perm_d, s);
+    if (e == hipSuccess && grid_cells(p) > 0) {
+        float* cells = (float*)(w + gen_perm_bytes(p));
+        T.maj = cells;
+        e = lp::launch_majorant_grid(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, T.grid_n, sm->lut,
+                                     sm->lut_size, sm->density_scale, vol->vmin, vol->vmax, cells, s);
+    }
+    return e;
 }
 
 int check_workspace(void* ws, size_t* ws_bytes, size_t need) {
@@ -244,25 +288,30 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     T.out = lf_out;
     T.dtype = dtype;
     char* w = (char*)ws;
-    float* sig = (float*)w;
-    unsigned int* ctr = (unsigned int*)(w + 64);
-    int32_t* perm_o = (int32_t*)(w + 256);
-    int32_t* perm_d = (int32_t*)(w + 256 + align256(4 * (size_t)(T.row_end - T.row_begin)));
-    T.sigbar = sig;
-    T.tile_ctr = ctr;
-    T.perm_o = perm_o;
-    T.perm_d = perm_d;
     T.vol = w + gen_order_bytes(params);
     const lf_medium* sm = sample ? sample : eval;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
-    if (e == hipSuccess)
-        e = lp::launch_wave_setup(T, sm->lut, sm->lut_size, sm->density_scale, params->majorant, sig, ctr, perm_o,
-                                  perm_d, s);
+    if (e == hipSuccess) e = setup_tracking(T, vol, sm, params, w, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate (set-up)");
     const int mode = (sample && sample != eval) ? lp::kFrozen : lp::kFwd;
     e = lp::launch_generate_wave(T, vol->type, mode, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate");
+    return LF_OK;
+}
+
+int lf_majorant_grid(const lf_volume* vol, const lf_medium* sample, const lf_gen_params* params, float* out,
+                     void* stream) {
+    g_err.clear();
+    int r;
+    if ((r = check_volume(vol)) || (r = check_medium(sample, "sample")) || (r = check_params(params, true))) return r;
+    if (!out) return fail(LF_E_ARG, "out is NULL");
+    const int G = params->majorant_grid;
+    if (G < 1) return fail(LF_E_ARG, "majorant_grid must be >= 1 for lf_majorant_grid");
+    hipError_t e = lp::launch_majorant_grid(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, G,
+                                            sample->lut, sample->lut_size, sample->density_scale, vol->vmin,
+                                            vol->vmax, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lf_majorant_grid");
     return LF_OK;
 }
 
@@ -293,24 +342,14 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     T.d_scale = d_scale;
     T.stats = nullptr;
     char* w = (char*)ws;
-    float* sig = (float*)w;
-    unsigned int* ctr = (unsigned int*)(w + 64);
-    int32_t* perm_o = (int32_t*)(w + 256);
-    int32_t* perm_d = (int32_t*)(w + 256 + align256(4 * (size_t)(T.row_end - T.row_begin)));
-    T.sigbar = sig;
-    T.tile_ctr = ctr;
-    T.ray_count = ctr + 8;
-    T.perm_o = perm_o;
-    T.perm_d = perm_d;
+    T.ray_count = (unsigned int*)(w + 64) + 8;
     T.ray_list = (uint32_t*)(w + gen_order_bytes(params));
     T.vol = w + gen_order_bytes(params) + list_bytes;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
     if (e == hipSuccess) e = lp::launch_zero(d_lut, 4ll * medium->lut_size, s);
     if (e == hipSuccess) e = lp::launch_zero(d_scale, 1, s);
-    if (e == hipSuccess)
-        e = lp::launch_wave_setup(T, medium->lut, medium->lut_size, medium->density_scale, params->majorant, sig,
-                                  ctr, perm_o, perm_d, s);
+    if (e == hipSuccess) e = setup_tracking(T, vol, medium, params, w, s);
     if (e == hipSuccess) e = lp::launch_active_rays(T, s);
     if (e == hipSuccess) e = lp::launch_generate_wave(T, vol->type, lp::kGrad, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate_backward");

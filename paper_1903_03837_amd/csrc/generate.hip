@@ -1,32 +1,15 @@
-// generate.hip -- small set-up kernels of light-field generation: the
-// default majorant, zero fill, and the copy of the volume into 4^3 bricks.
+// generate.hip -- small set-up kernels of light-field generation: zero fill,
+// the copy of the volume into 4^3 bricks, and the cell majorants of the
+// majorant grid.
 #include <hip/hip_fp16.h>
 
 #include "internal.hpp"
 
 namespace lp {
 
-__global__ void majorant_kernel(const float* lut, int n, float scale, float given, float* out) {
-    __shared__ float red[256];
-    float m = 0.0f;
-    for (int e = threadIdx.x; e < n; e += 256) m = fmaxf(m, lut[4 * e + 3]);
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = given > 0.0f ? given : 1.25f * scale * red[0];
-}
-
 __global__ void zero_kernel(float* p, long long n) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0f;
-}
-
-hipError_t launch_majorant(const float* lut, int lut_n, float scale, float given, float* out, hipStream_t s) {
-    majorant_kernel<<<1, 256, 0, s>>>(lut, lut_n, scale, given, out);
-    return hipGetLastError();
 }
 
 hipError_t launch_zero(float* p, long long n, hipStream_t s) {
@@ -73,6 +56,91 @@ hipError_t launch_brick4(const void* src, int vtype, int layout, int nx, int ny,
     else
         brick4_kernel<float><<<blocks, 256, 0, s>>>((const float*)src, layout, nx, ny, nz, nbx, nby, total,
                                                      (float*)dst);
+    return hipGetLastError();
+}
+
+// Majorant grid: one workgroup per cell (x fastest).  Every point of cell c
+// along an axis has grid coordinate g = x * n / extent - 1/2 in
+// [c n / G - 1/2, (c + 1) n / G - 1/2), so its trilinear footprint lies in
+// voxels floor(c n / G - 1/2) .. floor((c + 1) n / G - 1/2) + 1; one more
+// voxel on each side absorbs the FP32 rounding of the cell a point is
+// assigned to.  The raw range [lo, hi] of that block bounds the
+// interpolated value, and the LUT entries bracketing its window position
+// bound alpha.  Majorant = max(1.25 scale max alpha, global / 256).
+__device__ __forceinline__ int floor_div_i(int a, int b) {  // b > 0
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void majorant_grid_kernel(const T* vol, int layout, int nx, int ny, int nz, int G,
+                                                             const float* lut, int lut_n, float scale, double vmin,
+                                                             double vmax, float* out) {
+    __shared__ float rlo[1024], rhi[1024];
+    const int cell = blockIdx.x;
+    const int c[3] = {cell % G, (cell / G) % G, cell / (G * G)};
+    const int n[3] = {nx, ny, nz};
+    int lo[3], cnt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = max(floor_div_i(2 * c[a] * n[a] - G, 2 * G) - 1, 0);
+        const int hi = min(floor_div_i(2 * (c[a] + 1) * n[a] - G, 2 * G) + 2, n[a] - 1);
+        cnt[a] = hi - lo[a] + 1;
+    }
+    float vlo = 3.402823466e38f, vhi = -3.402823466e38f;
+    const int total = cnt[0] * cnt[1] * cnt[2];
+    for (int e = threadIdx.x; e < total; e += 1024) {
+        const int x = lo[0] + e % cnt[0], y = lo[1] + (e / cnt[0]) % cnt[1], z = lo[2] + e / (cnt[0] * cnt[1]);
+        long long at;
+        if (layout == 8)
+            at = ((x >> 3) + (long long)(nx >> 3) * ((y >> 3) + (long long)(ny >> 3) * (z >> 3))) * 512 + (x & 7) +
+                 8 * ((y & 7) + 8 * (z & 7));
+        else
+            at = x + (long long)nx * (y + (long long)ny * z);
+        const float v = (float)vol[at];
+        vlo = fminf(vlo, v);
+        vhi = fmaxf(vhi, v);
+    }
+    rlo[threadIdx.x] = vlo;
+    rhi[threadIdx.x] = vhi;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            rlo[threadIdx.x] = fminf(rlo[threadIdx.x], rlo[threadIdx.x + w]);
+            rhi[threadIdx.x] = fmaxf(rhi[threadIdx.x], rhi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    // window position of the range ends in double, as the definition states
+    const double last = (double)(lut_n - 1);
+    const double slo = fmin(fmax(((double)rlo[0] - vmin) / (vmax - vmin), 0.0), 1.0);
+    const double shi = fmin(fmax(((double)rhi[0] - vmin) / (vmax - vmin), 0.0), 1.0);
+    const int e0 = min((int)floor(slo * last), lut_n - 2);
+    const int e1 = min((int)floor(shi * last), lut_n - 2) + 1;
+    float amax = 0.0f, aall = 0.0f;
+    for (int e = 0; e < lut_n; ++e) {
+        const float a = lut[4 * e + 3];
+        aall = fmaxf(aall, a);
+        if (e >= e0 && e <= e1) amax = fmaxf(amax, a);
+    }
+    const double m = 1.25 * (double)scale * (double)amax;
+    const double fl = 1.25 * (double)scale * (double)aall / 256.0;
+    out[cell] = (float)(m > fl ? m : fl);
+}
+
+hipError_t launch_majorant_grid(const void* vol, int vtype, int layout, int nx, int ny, int nz, int G,
+                                const float* lut, int lut_n, float scale, double vmin, double vmax, float* out,
+                                hipStream_t s) {
+    const unsigned cells = (unsigned)(G * G * G);
+    if (vtype == 0)
+        majorant_grid_kernel<uint8_t><<<cells, 1024, 0, s>>>((const uint8_t*)vol, layout, nx, ny, nz, G, lut, lut_n,
+                                                             scale, vmin, vmax, out);
+    else if (vtype == 1)
+        majorant_grid_kernel<uint16_t><<<cells, 1024, 0, s>>>((const uint16_t*)vol, layout, nx, ny, nz, G, lut,
+                                                              lut_n, scale, vmin, vmax, out);
+    else
+        majorant_grid_kernel<float><<<cells, 1024, 0, s>>>((const float*)vol, layout, nx, ny, nz, G, lut, lut_n,
+                                                           scale, vmin, vmax, out);
     return hipGetLastError();
 }
 

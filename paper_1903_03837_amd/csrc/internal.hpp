@@ -35,11 +35,13 @@ struct LookupParams {
 
 hipError_t launch_points(int n, float* xyz, const float* query, long long nq, int K, int* idx, float* w,
                          hipStream_t s);
-hipError_t launch_majorant(const float* lut, int lut_n, float scale, float given, float* out, hipStream_t s);
 hipError_t launch_brick4(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst, hipStream_t s);
 hipError_t launch_wave_setup(const TraceParams& P, const float* sample_lut, int lut_n, float sample_scale,
                              float given, float* sigbar, unsigned int* ctr, int32_t* perm_o, int32_t* perm_d,
                              hipStream_t s);
+hipError_t launch_majorant_grid(const void* vol, int vtype, int layout, int nx, int ny, int nz, int G,
+                                const float* lut, int lut_n, float scale, double vmin, double vmax, float* out,
+                                hipStream_t s);
 hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipStream_t s);
 hipError_t launch_active_rays(const TraceParams& P, hipStream_t s);
 hipError_t launch_zero(float* p, long long n, hipStream_t s);

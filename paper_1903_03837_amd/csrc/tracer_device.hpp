@@ -6,7 +6,8 @@
 // deterministic.  Transport (the volumetric reading of Sec. 2's "conventional
 // path tracer"):
 //   - origin jitter on the disk of area 4 pi R^2 / M in the tangent plane;
-//   - delta tracking against a global majorant sigma_bar;
+//   - delta tracking against a majorant: one global sigma_bar, or a grid of
+//     cell majorants walked cell by cell;
 //   - real collision: throughput times the albedo, next-event estimation
 //     towards the light with ratio-tracking transmittance, Henyey-Greenstein
 //     direction for the next segment; escape: constant environment.
@@ -82,10 +83,54 @@ struct TraceParams {
     const int32_t* perm_o;
     const int32_t* perm_d;
     unsigned int* tile_ctr;
+    // majorant grid: grid_n^3 cell majorants (x fastest) over the volume box;
+    // grid_n = 1 with maj = sigbar is the global majorant
+    int32_t grid_n, nz;
+    float gcell[3];                  // cells per world unit
+    float gcw[3];                    // cell width
+    const float* maj;
     // adjoint: compacted list of rays with a nonzero adjoint and its length
     uint32_t* ray_list;
     unsigned int* ray_count;
 };
+
+// Ray tiles: 8 origins x 8 directions, taken in groups of 16 origin tiles
+// sweeping the direction tiles; the tile sequence is cut into 8 parts, one
+// per XCD (workgroups are dispatched round-robin over the XCDs).
+constexpr int kGroupTiles = 16;
+constexpr int kParts = 8;
+
+// Tile t of the row slab -> (origin tile, direction tile).
+__device__ __forceinline__ void tile_coords(long long t, int tiles_i, int tiles_j, int& ti, int& tj) {
+    const long long per_group = (long long)kGroupTiles * tiles_j;
+    const int gi = (int)(t / per_group);
+    const int gsz = min(kGroupTiles, tiles_i - gi * kGroupTiles);
+    const long long off = t - (long long)gi * per_group;
+    tj = (int)(off / gsz);
+    ti = gi * kGroupTiles + (int)(off - (long long)tj * gsz);
+}
+
+// Lane states of the persistent kernels.
+enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4, kShadow2 = 5 };
+
+// Next tile for a wave whose home part is `home`; -1 when all are taken.
+__device__ __forceinline__ long long next_tile(unsigned int* ctr, long long ntiles, int home, unsigned& dry) {
+    const long long part = (ntiles + kParts - 1) / kParts;
+    for (int q = 0; q < kParts; ++q) {
+        const int p = (home + q) % kParts;
+        if (dry & (1u << p)) continue;
+        const long long lo = (long long)p * part;
+        const long long n = min(part, ntiles - lo);
+        if (n <= 0) {
+            dry |= 1u << p;
+            continue;
+        }
+        const unsigned got = atomicAdd(&ctr[p], 1u);
+        if ((long long)got < n) return lo + got;
+        dry |= 1u << p;
+    }
+    return -1;
+}
 
 // Hardware reciprocal / reciprocal square root (1 ulp).  Used where the
 // result only moves a continuous quantity (slab bounds, frames, directions);
@@ -94,7 +139,7 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 struct Counters {
-    uint32_t tent, shadow, real, samples;
+    uint32_t tent, shadow, real, samples, cells;
 };
 
 // ---------------------------------------------------------------------------
@@ -220,6 +265,90 @@ __device__ __forceinline__ float hg_mu(float g, float u) {
 __device__ __forceinline__ float neg_log1m(float u) { return -__logf(1.0f - u); }
 
 // ---------------------------------------------------------------------------
+// Majorant-grid walk (3-D DDA over the grid_n^3 cells along x + t d).  The
+// exponential variate tau of a tentative collision is spent cell by cell at
+// each cell's majorant; a cell of majorant 0 spends none.
+// The walk is rebuilt from the point reached at the start of each iteration;
+// a point that rounds into a neighbouring cell only shortens that cell's
+// first piece (the cell majorants cover one voxel beyond each cell).
+// ---------------------------------------------------------------------------
+struct GridWalk {
+    float t, tx, ty, tz, dx, dy, dz;
+    int cx, cy, cz;
+
+    __device__ __forceinline__ void init(const TraceParams& P, f3 x, f3 d, float t0) {
+        const int G = P.grid_n;
+        const f3 p = fma3(d, t0, x);
+        const float pp[3] = {p.x, p.y, p.z}, dd[3] = {d.x, d.y, d.z}, xx[3] = {x.x, x.y, x.z};
+        int c[3];
+        float tm[3], dl[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            c[a] = min(max((int)floorf((pp[a] - P.bmin[a]) * P.gcell[a]), 0), G - 1);
+            if (fabsf(dd[a]) < 1e-20f) {
+                tm[a] = 3.402823466e38f;
+                dl[a] = 0.0f;
+            } else {
+                const float inv = rcp(dd[a]);
+                const float plane = fmaf((float)(c[a] + (dd[a] > 0.0f ? 1 : 0)), P.gcw[a], P.bmin[a]);
+                tm[a] = (plane - xx[a]) * inv;
+                dl[a] = P.gcw[a] * fabsf(inv);
+            }
+        }
+        t = t0;
+        cx = c[0];
+        cy = c[1];
+        cz = c[2];
+        tx = tm[0];
+        ty = tm[1];
+        tz = tm[2];
+        dx = dl[0];
+        dy = dl[1];
+        dz = dl[2];
+    }
+
+    // Next tentative point for tau: its t (and the majorant there in sb), or
+    // tend when the segment ends first.  The step is branch-free: the face
+    // crossed first is the one whose boundary equals the minimum, and cell
+    // indices are clamped to the grid, so a point that rounding carries past
+    // the last cell stays in it.  Every step raises the smallest boundary by
+    // one cell width along its axis, so the loop reaches tend within
+    // 3 (grid_n * segment length / cell width + 2) steps.
+    __device__ __forceinline__ float next(const TraceParams& P, const float* mg, f3 d, float tau, float tend,
+                                          float& sb, uint32_t& steps) {
+        const int G = P.grid_n, Gm = P.grid_n - 1;
+        const int sx = d.x > 0.0f ? 1 : -1, sy = d.y > 0.0f ? 1 : -1, sz = d.z > 0.0f ? 1 : -1;
+        float s, room;
+        bool hit;
+        for (;;) {
+            s = mg[(cz * G + cy) * G + cx];
+            const float tmin = fminf(fminf(tx, ty), tz);
+            const float te = fminf(tmin, tend);
+            room = s * fmaxf(te - t, 0.0f);
+            hit = tau < room;
+            if (hit || te >= tend) break;
+            tau -= room;
+            t = te;
+            ++steps;
+            const bool bx = tx == tmin, by = !bx && ty == tmin, bz = !bx && !by;
+            cx = min(max(cx + (bx ? sx : 0), 0), Gm);
+            cy = min(max(cy + (by ? sy : 0), 0), Gm);
+            cz = min(max(cz + (bz ? sz : 0), 0), Gm);
+            tx += bx ? dx : 0.0f;
+            ty += by ? dy : 0.0f;
+            tz += bz ? dz : 0.0f;
+        }
+        if (hit) {
+            t = fmaf(tau, rcp(s), t);
+            sb = s;
+            return t;
+        }
+        t = tend;
+        return tend;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Gradient accumulation (kGrad): per-lane cache of the alpha gradient of the
 // last LUT pair, flushed into the workgroup's LDS accumulator when the pair
 // changes; scale gradient kept in a register.
@@ -282,6 +411,12 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum64(uint32_t v) {
+    unsigned long long w = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+    return w;
 }
 __device__ __forceinline__ float wave_sumf(float v) {
 #pragma unroll

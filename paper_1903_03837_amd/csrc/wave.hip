@@ -9,7 +9,8 @@
 //     IDLE -> START -> FLIGHT <-> VERTEX -> SHADOW -> FLIGHT ... -> IDLE
 // and every loop iteration advances all lanes by one Philox4x32-10 block:
 //   START   pair 0 jitters the origin, pair 1 is the first tentative collision;
-//   FLIGHT  two tentative collisions (delta tracking);
+//   FLIGHT  two tentative collisions (delta tracking; the majorant grid is
+//           walked from the current point to each of them);
 //   VERTEX  light sample and phase-function words (NEE set-up);
 //   SHADOW  two ratio-tracking steps towards the light.
 // Both tentative points of a block are fetched before either is classified,
@@ -40,55 +41,25 @@
 
 namespace lp {
 
-enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4, kShadow2 = 5 };
-constexpr int kGroupTiles = 16;
-constexpr int kParts = 8;
-
-// Tile t of the row slab -> (origin tile, direction tile).
-__device__ __forceinline__ void tile_coords(long long t, int tiles_i, int tiles_j, int& ti, int& tj) {
-    const long long per_group = (long long)kGroupTiles * tiles_j;
-    const int gi = (int)(t / per_group);
-    const int gsz = min(kGroupTiles, tiles_i - gi * kGroupTiles);
-    const long long off = t - (long long)gi * per_group;
-    tj = (int)(off / gsz);
-    ti = gi * kGroupTiles + (int)(off - (long long)tj * gsz);
-}
-
-// Next tile for a wave whose home part is `home`; -1 when all are taken.
-__device__ __forceinline__ long long next_tile(unsigned int* ctr, long long ntiles, int home, unsigned& dry) {
-    const long long part = (ntiles + kParts - 1) / kParts;
-    for (int q = 0; q < kParts; ++q) {
-        const int p = (home + q) % kParts;
-        if (dry & (1u << p)) continue;
-        const long long lo = (long long)p * part;
-        const long long n = min(part, ntiles - lo);
-        if (n <= 0) {
-            dry |= 1u << p;
-            continue;
-        }
-        const unsigned got = atomicAdd(&ctr[p], 1u);
-        if ((long long)got < n) return lo + got;
-        dry |= 1u << p;
-    }
-    return -1;
-}
-
 template <int VT, int MODE>
-__global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
+__global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     extern __shared__ float4 smem[];
     float4* lut_e = smem;
     float4* lut_s = smem + (MODE == kFrozen ? P.lut_n : 0);
     float* glds = (float*)(smem + P.lut_n);  // kGrad: dLUT [lut_n][4], dscale
+    // cell majorants after the tables above
+    float* mg = (float*)smem + 4 * P.lut_n * (MODE == kFrozen ? 2 : 1) + (MODE == kGrad ? 4 * P.lut_n + 1 : 0);
+    const int ncell = P.grid_n * P.grid_n * P.grid_n;
     for (int e = threadIdx.x; e < P.lut_n; e += blockDim.x) {
         lut_e[e] = ((const float4*)P.lut_e)[e];
         if constexpr (MODE == kFrozen) lut_s[e] = ((const float4*)P.lut_s)[e];
     }
+    for (int e = threadIdx.x; e < ncell; e += blockDim.x) mg[e] = P.maj[e];
     if constexpr (MODE == kGrad)
         for (int e = threadIdx.x; e < 4 * P.lut_n + 1; e += blockDim.x) glds[e] = 0.0f;
     __syncthreads();
 
     const float sigbar = *P.sigbar;
-    const float inv_sigbar = sigbar > 0.0f ? 1.0f / sigbar : 0.0f;
     const uint32_t K0 = P.key0, K1 = P.key1;
     const int lane = threadIdx.x & 63;
     const int rows = P.row_end - P.row_begin;
@@ -114,7 +85,7 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
     int s = 0, b = 0;
     f3 po = mk3(0, 0, 0), d0 = po, acc = po, x = po, dir = po, T = po, L = po, om = po, C = po;
     float W = 1.0f, t = 0.0f, tend = 0.0f, Tr = 1.0f, up0 = 0.0f, up1 = 0.0f;
-    Counters cnt = {0, 0, 0, 0};
+    Counters cnt = {0, 0, 0, 0, 0};
     // adjoint state: texel adjoint / spp, pass A radiance, pass, NEE score weight
     f3 adj = po, ltot = po;
     int pass = 0;
@@ -279,9 +250,14 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
         te.a = te.a_s = 0.0f;
         te.rgb = mk3(0.0f, 0.0f, 0.0f);
         if (stepA || stepB) {
+            // (stepB always holds here; stepA is off for the first point of a sample)
             const f3 sd = mode == kFlight ? dir : om;
-            const float tA = fmaf(neg_log1m(u01(r.x)), inv_sigbar, t);
-            const float tB = fmaf(neg_log1m(u01(r.z)), inv_sigbar, stepA ? tA : t);
+            GridWalk gw;
+            gw.init(P, x, sd, t);
+            float sbA = 0.0f, sbB = 0.0f, tA = t;
+            if (stepA) tA = gw.next(P, mg, sd, neg_log1m(u01(r.x)), tend, sbA, cnt.cells);
+            const float tB = (stepA && tA >= tend) ? tend
+                                                   : gw.next(P, mg, sd, neg_log1m(u01(r.z)), tend, sbB, cnt.cells);
             const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
             const float rawA = sample_volume<VT>(P, yA);
             const float rawB = sample_volume<VT>(P, yB);
@@ -298,11 +274,12 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                 }
                 const TF tf = classify<MODE>(P, lut_e, lut_s, h ? rawB : rawA);
                 const float sig_e = P.scale_e * tf.a;
+                const float sb = h ? sbB : sbA;  // majorant of the point's cell
                 t = th;
                 if (mode == kFlight) {
                     cnt.tent++;
                     const float sig_s = MODE == kFrozen ? P.scale_s * tf.a_s : sig_e;
-                    if (u01(h ? r.w : r.y) * sigbar < sig_s) {
+                    if (u01(h ? r.w : r.y) * sb < sig_s) {
                         ev_real = true;
                         more = false;
                         ynew = h ? yB : yA;
@@ -311,15 +288,15 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
                         if constexpr (MODE == kGrad)
                             if (pass) G.sigma(tf, P.scale_e, dot(adj, ltot - L) / sig_e);
                     } else {
-                        if constexpr (MODE == kFrozen) W *= (sigbar - sig_e) / (sigbar - sig_s);
+                        if constexpr (MODE == kFrozen) W *= (sb - sig_e) / (sb - sig_s);
                         if constexpr (MODE == kGrad)
-                            if (pass) G.sigma(tf, P.scale_e, -dot(adj, ltot - L) / (sigbar - sig_e));
+                            if (pass) G.sigma(tf, P.scale_e, -dot(adj, ltot - L) / (sb - sig_e));
                     }
                 } else if (mode == kShadow) {
                     cnt.shadow++;
-                    Tr *= 1.0f - sig_e * inv_sigbar;
+                    Tr *= 1.0f - sig_e * rcp(sb);
                 } else {
-                    if constexpr (MODE == kGrad) G.sigma(tf, P.scale_e, -rc / (sigbar - sig_e));
+                    if constexpr (MODE == kGrad) G.sigma(tf, P.scale_e, -rc / (sb - sig_e));
                 }
             }
             if (ev_end) {
@@ -446,11 +423,13 @@ __global__ __launch_bounds__(256) void gen_wave_kernel(TraceParams P) {
     if (P.stats) {
         const uint32_t a = wave_sum(cnt.tent), c = wave_sum(cnt.shadow), e = wave_sum(cnt.real),
                        f = wave_sum(cnt.samples);
+        const unsigned long long cs = wave_sum64(cnt.cells);
         if (lane == 0) {
             atomicAdd(&P.stats[0], (unsigned long long)a);
             atomicAdd(&P.stats[1], (unsigned long long)c);
             atomicAdd(&P.stats[2], (unsigned long long)e);
             atomicAdd(&P.stats[3], (unsigned long long)f);
+            atomicAdd(&P.stats[4], cs);
         }
     }
 }
@@ -548,8 +527,9 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
     const long long ntiles = ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
     if (ntiles <= 0) return hipSuccess;
+    const size_t ncell = (size_t)P.grid_n * P.grid_n * P.grid_n;
     const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
-                       (MODE == kGrad ? sizeof(float) * (4 * (size_t)P.lut_n + 1) : 0);
+                       (MODE == kGrad ? sizeof(float) * (4 * (size_t)P.lut_n + 1) : 0) + sizeof(float) * ncell;
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -557,8 +537,8 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE>, 256, lds);
     if (e != hipSuccess) return e;
     long long blocks = (long long)cus * (per_cu > 0 ? per_cu : 1);
-    // at least one tile per wave (the adjoint's list length is only known on
-    // the device; its waves that find no chunk exit at once)
+    // at least one tile per wave (list lengths are only known on the device;
+    // waves that find no chunk exit at once)
     const long long need = (ntiles + 3) / 4;
     if (blocks > need) blocks = need;
     gen_wave_kernel<VT, MODE><<<(unsigned)blocks, 256, lds, s>>>(P);

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header(lp):
     assert C.sizeof(lp._Volume) == 64
     assert C.sizeof(lp._Medium) == 16
     assert C.sizeof(lp._Light) == 76
-    assert C.sizeof(lp._GenParams) == 80
+    assert C.sizeof(lp._GenParams) == 88
     assert C.sizeof(lp._Camera) == 40
 
 
@@ -88,6 +88,26 @@ def test_workspace_size_query(lp):
     assert r == LF_OK and sz == 256 + 256 + 256 + 4096
 
 
+def test_workspace_size_with_majorant_grid(lp):
+    vol, med, light, prm = scene(lp)
+    prm.majorant_grid = 16
+    r, sz = call_generate(lp, vol, med, light, prm)
+    # the 16^3 cell majorants (16 KiB) sit between the spatial orders and the brick copy
+    assert r == LF_OK and sz == 256 + 256 + 256 + 16384 + 4096
+    prm.majorant = 2.0  # a fixed global majorant needs no grid
+    assert call_generate(lp, vol, med, light, prm)[1] == 256 + 256 + 256 + 4096
+
+
+def test_majorant_grid_rejects(lp):
+    vol, med, light, prm = scene(lp)
+    L = lp.library()
+    assert L.lf_majorant_grid(C.byref(vol), C.byref(med), C.byref(prm), FAKE, None) == LF_E_ARG  # grid 0
+    prm.majorant_grid = 17
+    assert L.lf_majorant_grid(C.byref(vol), C.byref(med), C.byref(prm), FAKE, None) == LF_E_ARG
+    prm.majorant_grid = 4
+    assert L.lf_majorant_grid(C.byref(vol), C.byref(med), C.byref(prm), None, None) == LF_E_ARG
+
+
 @pytest.mark.parametrize("mutate,code,msg", [
     (lambda v, m, l, p: setattr(v, "data", None), LF_E_ARG, "data"),
     (lambda v, m, l, p: setattr(v, "type", 7), LF_E_ARG, "voxel type"),
@@ -108,6 +128,10 @@ def test_workspace_size_query(lp):
     (lambda v, m, l, p: setattr(p, "radius", 0.0), LF_E_ARG, "radius"),
     (lambda v, m, l, p: setattr(p, "max_bounces", 0), LF_E_ARG, "max_bounces"),
     (lambda v, m, l, p: (setattr(p, "row_begin", 10), setattr(p, "row_end", 5)), LF_E_ARG, "row range"),
+    (lambda v, m, l, p: setattr(p, "majorant_grid", 17), LF_E_ARG, "majorant_grid"),
+    (lambda v, m, l, p: setattr(p, "majorant_grid", -1), LF_E_ARG, "majorant_grid"),
+    (lambda v, m, l, p: setattr(p, "origin_rows", 65), LF_E_ARG, "origin_rows"),
+    (lambda v, m, l, p: (setattr(p, "origin_rows", 32), setattr(p, "row_end", 40)), LF_E_ARG, "row range"),
 ])
 def test_generate_rejects(lp, mutate, code, msg):
     vol, med, light, prm = scene(lp)

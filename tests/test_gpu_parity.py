@@ -63,7 +63,7 @@ def nondegenerate(M, N, ks):
 
 def gpu_field(lp, sc, dtype="f32", sample=None, stats=False):
     vol, med, light, prm, _ = lp.device_scene(sc)
-    st = torch.zeros(4, dtype=torch.int64, device="cuda") if stats else None
+    st = torch.zeros(5, dtype=torch.int64, device="cuda") if stats else None
     smp = None
     if sample is not None:
         smp = lp.Medium(torch.from_numpy(sample.lut).cuda(), sample.scale)
@@ -183,6 +183,45 @@ def test_generate_ragged_and_tiny(lp, orc):
             assert np.all(got[ks[(ks // N) == (ks % N)]] == 0.0)
         if len(nd) and np.abs(ref[nd]).sum() > 0:
             assert rel_l1(got[nd], ref[nd]) <= RAD_TOL, (M, N)
+
+
+# ------------------------------------------------------------ majorant grid
+@pytest.mark.parametrize("c,G,vol_n", [(1, 16, None), (1, 7, None), (2, 16, 64), (3, 16, 64), (5, 11, 32)])
+def test_majorant_grid_matches_oracle(lp, orc, c, G, vol_n):
+    """Cell majorants: the oracle's FP64 values rounded once to FP32 (u8
+    linear, u16 linear, u16 in 8^3 bricks, f32; G dividing n or not)."""
+    sc = S.config(c, vol_n=vol_n) if vol_n else S.config(c)
+    sc = sc.with_params(grid=G)
+    vol, med, _, prm, _ = lp.device_scene(sc)
+    got = lp.majorant_grid(vol, med, prm).cpu().numpy()
+    ref = orc.majorant_grid(sc.volume, sc.medium, sc.params).astype(np.float32)
+    assert np.array_equal(got, ref)
+
+
+def test_generate_global_majorant(lp, orc):
+    """grid = 0 tracks against the one global majorant."""
+    sc = S.config(1, M=96, N=96, spp=8, grid=0)
+    got, st = gpu_field(lp, sc, stats=True)
+    ks = np.arange(96 * 96)
+    ref, ost = orc.generate(sc, ks, stats=True)
+    nd = nondegenerate(96, 96, ks)
+    assert rel_l1(got[nd], ref[nd]) <= RAD_TOL
+    assert abs(st[0] / ost[0] - 1) < 1e-3 and st[4] == 0  # one cell: the walk never steps
+
+
+def test_grid_cuts_tentative_collisions(lp, orc):
+    """On the CT-like phantom a 16^3 grid cuts the tentative collisions many
+    times over; each estimator matches the oracle's of the same kind (their
+    agreement in expectation is pinned on the oracle)."""
+    sc = S.config(2, M=128, N=128, spp=8, grid=16)
+    a, sa = gpu_field(lp, sc.with_params(grid=0), stats=True)
+    b, sb = gpu_field(lp, sc, stats=True)
+    print(f"tentative collisions: global {sa[0]}, grid {sb[0]} ({sa[0] / sb[0]:.1f}x); "
+          f"shadow steps {sa[1]} -> {sb[1]}; cell steps {sb[4]}")
+    assert sa[0] > 5 * sb[0] and sa[2] > 0
+    ks = S.random_rays(128, 128, 1500, 9)
+    assert rel_l1(a[ks], orc.generate(sc.with_params(grid=0), ks)) <= RAD_TOL
+    assert rel_l1(b[ks], orc.generate(sc, ks)) <= RAD_TOL
 
 
 def test_row_slabs_bit_identical(lp):
@@ -474,6 +513,43 @@ def test_backward_matches_finite_differences(lp, orc):
     mask[-1] = True
     err = np.linalg.norm(fd[mask] - g[mask]) / np.linalg.norm(g[mask])
     print(f"adjoint vs central differences on {mask.sum()} coordinates: {err:.2e}")
+    assert err <= 1e-2
+
+
+def test_backward_with_grid_matches_finite_differences(lp, orc):
+    """As above with the majorant grid, built from the reference medium in
+    both the frozen-sampling forward and the adjoint."""
+    sc = grad_scene()
+    assert sc.params.grid > 0 and sc.params.majorant == 0.0
+    M = N = 48
+    rng = np.random.default_rng(14)
+    adj = rng.standard_normal((M * N, 3))
+    adj[np.arange(M) * (N + 1)] = 0.0
+    vol, med, light, prm, _ = lp.device_scene(sc)
+    d_lut, d_scale = lp.generate_backward(vol, med, light, prm, torch.from_numpy(adj.astype(np.float32)).cuda())
+    g = np.concatenate([d_lut.cpu().numpy().reshape(-1), d_scale.cpu().numpy()]).astype(np.float64)
+    theta0 = sc.medium
+    smp = lp.Medium(torch.from_numpy(theta0.lut).cuda(), theta0.scale)
+
+    def loss(lut, scale):
+        m = lp.Medium(torch.from_numpy(lut).cuda(), scale)
+        L = lp.generate(vol, m, light, prm, sample=smp).double().cpu().numpy().reshape(-1, 3)
+        return float((L * adj).sum())
+
+    h = 1e-3
+    fd = np.zeros_like(g)
+    touched = np.argwhere(np.abs(g[:-1].reshape(-1, 4)) > 1e-4 * np.abs(g).max())
+    for e, c in touched:
+        lp_, lm = theta0.lut.copy(), theta0.lut.copy()
+        lp_[e, c] += h
+        lm[e, c] -= h
+        fd[4 * e + c] = (loss(lp_, theta0.scale) - loss(lm, theta0.scale)) / (float(lp_[e, c]) - float(lm[e, c]))
+    fd[-1] = (loss(theta0.lut, theta0.scale + h) - loss(theta0.lut, theta0.scale - h)) / (2 * h)
+    mask = np.zeros_like(g, bool)
+    mask[[4 * e + c for e, c in touched]] = True
+    mask[-1] = True
+    err = np.linalg.norm(fd[mask] - g[mask]) / np.linalg.norm(g[mask])
+    print(f"grid adjoint vs central differences on {mask.sum()} coordinates: {err:.2e}")
     assert err <= 1e-2
 
 
