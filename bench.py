@@ -59,7 +59,7 @@ def measured_traffic(kernel_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(scene, seconds, nrays_probe=2000):
+def cpu_baseline(scene, seconds, nrays_probe=20000):
     """The FP64 oracle on a bounded seeded sample of the same rays."""
     import numpy as np
 

@@ -415,7 +415,7 @@ typedef struct {
     const orc_params* prm;
     double sigbar;
     int32_t grid;     /* cells per axis of the majorant grid, 0: global sigbar */
-    double* maj;      /* [grid^3] cell majorants */
+    const double* maj;/* [grid^3] cell majorants (shared by the call's threads) */
     int frozen;       /* sample medium differs from eval medium */
     int light_on;     /* light radiance not all zero */
     /* gradient accumulation (NULL in plain forward mode) */
@@ -700,8 +700,19 @@ typedef struct {
     double* g_lut;           /* per-thread gradient */
 } job;
 
+/* The majorant grid of a call is built once and shared by its threads. */
+static double* build_grid(const orc_volume* vol, const orc_medium* eval, const orc_medium* sample,
+                          const orc_params* prm) {
+    if (prm->majorant > 0.0 || prm->grid <= 0) return NULL;
+    size_t G = (size_t)prm->grid;
+    double* maj = (double*)malloc(sizeof(double) * G * G * G);
+    orc_majorant_grid(vol, sample ? sample : eval, prm, maj);
+    return maj;
+}
+
 static void tracer_setup(tracer* tr, const orc_volume* vol, const orc_medium* eval,
-                         const orc_medium* sample, const orc_light* light, const orc_params* prm) {
+                         const orc_medium* sample, const orc_light* light, const orc_params* prm,
+                         double* maj) {
     memset(tr, 0, sizeof(*tr));
     tr->vol = vol;
     tr->eval = eval;
@@ -709,11 +720,8 @@ static void tracer_setup(tracer* tr, const orc_volume* vol, const orc_medium* ev
     tr->light = light;
     tr->prm = prm;
     tr->sigbar = orc_majorant(tr->samp, prm);
-    tr->grid = prm->majorant > 0.0 ? 0 : prm->grid;
-    if (tr->grid > 0) {
-        tr->maj = (double*)malloc(sizeof(double) * (size_t)tr->grid * tr->grid * tr->grid);
-        orc_majorant_grid(vol, tr->samp, prm, tr->maj);
-    }
+    tr->grid = maj ? prm->grid : 0;
+    tr->maj = maj;
     tr->frozen = sample != NULL && sample != eval;
     tr->light_on = light->radiance[0] != 0.0 || light->radiance[1] != 0.0 || light->radiance[2] != 0.0;
 }
@@ -762,16 +770,17 @@ void orc_generate(const orc_volume* vol, const orc_medium* eval, const orc_mediu
                   const orc_light* light, const orc_params* prm, const int64_t* rays, int64_t nrays,
                   double* out, int32_t nthreads, double* stats) {
     if (nthreads < 1) nthreads = 1;
+    double* maj = build_grid(vol, eval, sample, prm);
     job* jobs = (job*)calloc((size_t)nthreads, sizeof(job));
     for (int32_t t = 0; t < nthreads; ++t) {
-        tracer_setup(&jobs[t].tr, vol, eval, sample, light, prm);
+        tracer_setup(&jobs[t].tr, vol, eval, sample, light, prm, maj);
         jobs[t].rays = rays;
         jobs[t].r0 = nrays * t / nthreads;
         jobs[t].r1 = nrays * (t + 1) / nthreads;
         jobs[t].out = out;
     }
     run_jobs(jobs, nthreads);
-    for (int32_t t = 0; t < nthreads; ++t) free(jobs[t].tr.maj);
+    free(maj);
     if (stats) {
         for (int a = 0; a < 4; ++a) stats[a] = 0.0;
         for (int32_t t = 0; t < nthreads; ++t)
@@ -785,9 +794,10 @@ void orc_gradient(const orc_volume* vol, const orc_medium* med, const orc_light*
                   double* d_lut, double* d_scale, int32_t nthreads) {
     if (nthreads < 1) nthreads = 1;
     int n = med->lut_size;
+    double* maj = build_grid(vol, med, NULL, prm);
     job* jobs = (job*)calloc((size_t)nthreads, sizeof(job));
     for (int32_t t = 0; t < nthreads; ++t) {
-        tracer_setup(&jobs[t].tr, vol, med, NULL, light, prm);
+        tracer_setup(&jobs[t].tr, vol, med, NULL, light, prm, maj);
         jobs[t].tr.s_alpha = (double*)calloc((size_t)n, sizeof(double));
         jobs[t].tr.s_rgb = (double*)calloc((size_t)3 * n, sizeof(double));
         jobs[t].tr.sh_alpha = (double*)calloc((size_t)n, sizeof(double));
@@ -809,8 +819,8 @@ void orc_gradient(const orc_volume* vol, const orc_medium* med, const orc_light*
         free(jobs[t].tr.s_rgb);
         free(jobs[t].tr.sh_alpha);
         free(jobs[t].tr.g_lut);
-        free(jobs[t].tr.maj);
     }
+    free(maj);
     free(jobs);
 }
 
