@@ -4,7 +4,7 @@
 One step = one pass of the whole path over the CT-like workload (256^3 u16
 phantom, M = N = 2048 spherical-Fibonacci points, 4.19M rays, 64 samples per
 ray, 8 bounces, HG g = 0.3, area light):
-  lf_points (SF table) -> lf_generate (FP32 light field, 4^3 majorant grid) -> lf_lookup (32 views
+  lf_points (SF table) -> lf_generate (FP32 light field, 5^3 majorant grid) -> lf_lookup (32 views
   of 1920 x 1080, K = 5) -> L2 view loss gradient -> lf_lookup adjoint ->
   lf_generate_backward (d LUT, d density scale).
 `value` = M*N*spp path samples per second of the whole step.  One JSON line
@@ -205,7 +205,7 @@ def main():
         "data": "synthetic (seeded CT-like phantom, transfer function, area light, cameras)",
         "config": {
             "workload": "CT-like phantom 256^3 u16 (12 nested ellipsoids), M=N=2048 SF points (4.19M rays), "
-                        "64 spp, 8 bounces, HG g=0.3, area light, 4^3 majorant grid, FP32 light field; lookup of "
+                        "64 spp, 8 bounces, HG g=0.3, area light, 5^3 majorant grid, FP32 light field; lookup of "
                         "32 views 1920x1080 K=5; adjoint of an L2 view loss",
             "M": M, "N": N, "spp": spp, "max_bounces": prm.max_bounces, "views": V, "width": W, "height": H,
             "K": K, "volume": "256^3 u16 linear", "majorant_grid": prm.grid,

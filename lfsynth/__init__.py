@@ -316,7 +316,7 @@ def config(c: int, **over) -> Scene:
     elif c == 2:
         vol = _phantom(vol_n or 256, 1002, 12, 0)
         lt = area_light(3002, R)
-        prm = Params(M=2048, N=2048, radius=R, spp=64, max_bounces=8, g=0.3, seed=4002, grid=4)
+        prm = Params(M=2048, N=2048, radius=R, spp=64, max_bounces=8, g=0.3, seed=4002, grid=5)
         nv, w, h = 32, 1920, 1080
     elif c in (3, 4):
         vol = _phantom(vol_n or 512, 1003, 40, 8)
@@ -329,7 +329,7 @@ def config(c: int, **over) -> Scene:
     elif c == 5:
         vol = _blob(vol_n or 128, 1005, F32)
         lt = directional_light(3005)
-        prm = Params(M=1024, N=1024, radius=R, spp=32, max_bounces=4, g=0.0, seed=4005, grid=5)
+        prm = Params(M=1024, N=1024, radius=R, spp=32, max_bounces=4, g=0.0, seed=4005, grid=8)
         nv, w, h = 16, 512, 512
     else:
         raise ValueError(f"unknown workload {c}")

@@ -100,14 +100,17 @@ struct TraceParams {
 constexpr int kGroupTiles = 16;
 constexpr int kParts = 8;
 
-// Tile t of the row slab -> (origin tile, direction tile).
+// Tile t of the row slab -> (origin tile, direction tile).  Tile counts are
+// below 2^32 (M, N <= 65535), so 32-bit unsigned division suffices.
 __device__ __forceinline__ void tile_coords(long long t, int tiles_i, int tiles_j, int& ti, int& tj) {
-    const long long per_group = (long long)kGroupTiles * tiles_j;
-    const int gi = (int)(t / per_group);
-    const int gsz = min(kGroupTiles, tiles_i - gi * kGroupTiles);
-    const long long off = t - (long long)gi * per_group;
-    tj = (int)(off / gsz);
-    ti = gi * kGroupTiles + (int)(off - (long long)tj * gsz);
+    const uint32_t tu = (uint32_t)t;
+    const uint32_t per_group = (uint32_t)kGroupTiles * (uint32_t)tiles_j;
+    const uint32_t gi = tu / per_group;
+    const uint32_t gsz = (uint32_t)min(kGroupTiles, tiles_i - (int)gi * kGroupTiles);
+    const uint32_t off = tu - gi * per_group;
+    const uint32_t q = off / gsz;
+    tj = (int)q;
+    ti = (int)(gi * kGroupTiles + (off - q * gsz));
 }
 
 // Lane states of the persistent kernels.
@@ -307,44 +310,61 @@ struct GridWalk {
         dz = dl[2];
     }
 
-    // Next tentative point for tau: its t (and the majorant there in sb), or
-    // tend when the segment ends first.  The step is branch-free: the face
-    // crossed first is the one whose boundary equals the minimum, and cell
-    // indices are clamped to the grid, so a point that rounding carries past
-    // the last cell stays in it.  Every step raises the smallest boundary by
-    // one cell width along its axis, so the loop reaches tend within
-    // 3 (grid_n * segment length / cell width + 2) steps.
-    __device__ __forceinline__ float next(const TraceParams& P, const float* mg, f3 d, float tau, float tend,
-                                          float& sb, uint32_t& steps) {
+    // Both tentative points of one iteration in a single walk: point A for
+    // tauA (when wantA), then point B for tauB from A.  One loop instead of
+    // two keeps the wave's trip count at the maximum over lanes of the cells
+    // both points need, not the sum of two maxima.  Points past the segment
+    // come back as tend, with the majorant of their cell in sbA / sbB.  The
+    // step is branch-free: the face crossed first is the one whose boundary
+    // equals the minimum, and cell indices are clamped to the grid, so a
+    // point that rounding carries past the last cell stays in it.  Every step
+    // raises the smallest boundary by one cell width along its axis, so the
+    // loop reaches tend within 3 (grid_n * segment length / cell width + 2)
+    // steps.
+    __device__ __forceinline__ void next2(const TraceParams& P, const float* mg, f3 d, bool wantA, float tauA,
+                                          float tauB, float tend, float& tA, float& sbA, float& tB, float& sbB,
+                                          uint32_t& steps) {
         const int G = P.grid_n, Gm = P.grid_n - 1;
         const int sx = d.x > 0.0f ? 1 : -1, sy = d.y > 0.0f ? 1 : -1, sz = d.z > 0.0f ? 1 : -1;
-        float s, room;
-        bool hit;
+        int phase = wantA ? 0 : 1;  // 0: looking for A, 1: looking for B, 2: done
+        float tau = wantA ? tauA : tauB;
+        tA = t;
+        tB = tend;
         for (;;) {
-            s = mg[(cz * G + cy) * G + cx];
+            const float s = mg[(cz * G + cy) * G + cx];
             const float tmin = fminf(fminf(tx, ty), tz);
             const float te = fminf(tmin, tend);
-            room = s * fmaxf(te - t, 0.0f);
-            hit = tau < room;
-            if (hit || te >= tend) break;
-            tau -= room;
-            t = te;
-            ++steps;
-            const bool bx = tx == tmin, by = !bx && ty == tmin, bz = !bx && !by;
-            cx = min(max(cx + (bx ? sx : 0), 0), Gm);
-            cy = min(max(cy + (by ? sy : 0), 0), Gm);
-            cz = min(max(cz + (bz ? sz : 0), 0), Gm);
-            tx += bx ? dx : 0.0f;
-            ty += by ? dy : 0.0f;
-            tz += bz ? dz : 0.0f;
+            const float room = s * fmaxf(te - t, 0.0f);
+            if (tau < room) {
+                t = fmaf(tau, rcp(s), t);
+                if (phase == 0) {
+                    tA = t;
+                    sbA = s;
+                    tau = tauB;
+                } else {
+                    tB = t;
+                    sbB = s;
+                }
+                ++phase;
+            } else {
+                tau -= room;
+                if (te >= tend) {
+                    if (phase == 0) tA = tend;
+                    phase = 2;
+                } else {
+                    t = te;
+                    ++steps;
+                    const bool bx = tx == tmin, by = !bx && ty == tmin, bz = !bx && !by;
+                    cx = min(max(cx + (bx ? sx : 0), 0), Gm);
+                    cy = min(max(cy + (by ? sy : 0), 0), Gm);
+                    cz = min(max(cz + (bz ? sz : 0), 0), Gm);
+                    tx += bx ? dx : 0.0f;
+                    ty += by ? dy : 0.0f;
+                    tz += bz ? dz : 0.0f;
+                }
+            }
+            if (phase == 2) break;
         }
-        if (hit) {
-            t = fmaf(tau, rcp(s), t);
-            sb = s;
-            return t;
-        }
-        t = tend;
-        return tend;
     }
 };
 

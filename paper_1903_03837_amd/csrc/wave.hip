@@ -254,10 +254,8 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
             const f3 sd = mode == kFlight ? dir : om;
             GridWalk gw;
             gw.init(P, x, sd, t);
-            float sbA = 0.0f, sbB = 0.0f, tA = t;
-            if (stepA) tA = gw.next(P, mg, sd, neg_log1m(u01(r.x)), tend, sbA, cnt.cells);
-            const float tB = (stepA && tA >= tend) ? tend
-                                                   : gw.next(P, mg, sd, neg_log1m(u01(r.z)), tend, sbB, cnt.cells);
+            float sbA = 0.0f, sbB = 0.0f, tA, tB;
+            gw.next2(P, mg, sd, stepA, neg_log1m(u01(r.x)), neg_log1m(u01(r.z)), tend, tA, sbA, tB, sbB, cnt.cells);
             const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
             const float rawA = sample_volume<VT>(P, yA);
             const float rawB = sample_volume<VT>(P, yB);
