@@ -184,6 +184,34 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
               int32_t n_views, int32_t W, int32_t H, int32_t K, int32_t mode, float* img,
               float* d_lf, int32_t* nn_out, void* stream);
 
+/* Ground-truth views: the path tracer of lf_generate along pinhole camera
+ * rays, the reference the paper compares its light-field views with (Sec. 4
+ * evaluation).  For each pixel (x, y) of each of the n_views cameras (host
+ * array, consumed before return; pixel centres, row 0 at the top, as in
+ * lf_lookup) img[((v * H + y) * W + x) * 3 + c] (device float32) receives
+ * the mean over params->spp samples of the radiance along the ray from the
+ * eye through the pixel centre.  The ray starts at the eye with no jitter;
+ * the random streams are those of a light-field ray with key
+ * (v * H + y) * W + x.  Uses spp, max_bounces, hg_g, majorant,
+ * majorant_grid and seed of params (M, N, center, radius, jitter and the
+ * row range are ignored).  n_views * W * H < 2^32.  Workspace as for
+ * lf_generate (size query with ws == NULL). */
+int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_light* light,
+                    const lf_gen_params* params, const lf_camera* cams, int32_t n_views, int32_t W, int32_t H,
+                    float* img, void* ws, size_t* ws_bytes, void* stream);
+
+/* Mean SSIM (Wang et al. 2004; the image index the paper reports in its
+ * evaluation) of n_images pairs of RGB float32 images a, b (device,
+ * [n_images][H][W][3]): 11 x 11 Gaussian window of sigma 1.5 normalised to
+ * sum 1, C1 = (0.01 data_range)^2, C2 = (0.03 data_range)^2, SSIM terms at
+ * every window position inside the image ((W - 10) x (H - 10) per channel),
+ * averaged over positions and the three channels.  out: device float64
+ * [n_images].  W, H >= 11, 1 <= n_images <= 21845.  The result does not
+ * depend on scheduling (fixed-order FP64 sums of FP32 terms).  Workspace:
+ * size query with ws == NULL. */
+int lf_ssim(const float* a, const float* b, int32_t n_images, int32_t W, int32_t H, float data_range, double* out,
+            void* ws, size_t* ws_bytes, void* stream);
+
 /* Cell majorants of the majorant grid that lf_generate and
  * lf_generate_backward track against (piecewise-constant majorant; the grid
  * and its bound are defined with lf_gen_params): out (device float

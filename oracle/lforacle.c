@@ -528,31 +528,16 @@ static int next_tentative(const piece* pc, int np, double* t, double tau, double
     return 0;
 }
 
-static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t s, double L[3]) {
+/* One path sample of stream key k, sample s, from x0 along the unit d0: the
+ * path tracer of Sec. 2 (volumetric reading) with the random-number layout
+ * described above. */
+static void trace_path(tracer* tr, uint32_t k, uint32_t s, const double x0[3], const double d0[3], double L[3]) {
     const orc_params* P = tr->prm;
     const orc_light* lt = tr->light;
     const double* bmin = tr->vol->box_min;
     const double* bmax = tr->vol->box_max;
     double sigbar = tr->sigbar;   /* majorant in force at the current tentative point */
-    double po[3], pd[3], dir[3], x[3];
-    orc_sf_point(P->M, i, po);
-    orc_sf_point(P->N, j, pd);
-    /* d_ij = p^d_j - p^o_i, normalised (Sec. 2, ray equation) */
-    sub3(pd, po, dir);
-    normalize3(dir);
-    /* ray origin O + R p^o_i, jittered on a disk of area A_S / M = 4 pi R^2 / M
-     * (radius 2R / sqrt M) in the tangent plane of S at p^o_i */
-    for (int a = 0; a < 3; ++a) x[a] = P->center[a] + P->radius * po[a];
-    if (P->jitter) {
-        ustream uj;
-        us_init(&uj, P->seed, k, s, 0, P_FLIGHT);
-        double u0 = us_get(&uj, 0), u1 = us_get(&uj, 1);
-        double rho = 2.0 * P->radius / sqrt((double)P->M) * sqrt(u0);
-        double ang = 2.0 * PI * u1;
-        double t1[3], t2[3];
-        orc_frame(po, t1, t2);
-        for (int a = 0; a < 3; ++a) x[a] += rho * (cos(ang) * t1[a] + sin(ang) * t2[a]);
-    }
+    double dir[3] = {d0[0], d0[1], d0[2]}, x[3] = {x0[0], x0[1], x0[2]};
     double T[3] = {1.0, 1.0, 1.0};
     double W = 1.0;
     L[0] = L[1] = L[2] = 0.0;
@@ -686,6 +671,31 @@ static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t 
         for (int a = 0; a < 3; ++a) nd[a] = st * cos(ph) * t1[a] + st * sin(ph) * t2[a] + mu * dir[a];
         dir[0] = nd[0]; dir[1] = nd[1]; dir[2] = nd[2];
     }
+}
+
+/* Ray r_k of the SF ray set (Sec. 2, ray equation), sample s. */
+static void trace_sample(tracer* tr, uint32_t k, int64_t i, int64_t j, uint32_t s, double L[3]) {
+    const orc_params* P = tr->prm;
+    double po[3], pd[3], dir[3], x[3];
+    orc_sf_point(P->M, i, po);
+    orc_sf_point(P->N, j, pd);
+    /* d_ij = p^d_j - p^o_i, normalised (Sec. 2, ray equation) */
+    sub3(pd, po, dir);
+    normalize3(dir);
+    /* ray origin O + R p^o_i, jittered on a disk of area A_S / M = 4 pi R^2 / M
+     * (radius 2R / sqrt M) in the tangent plane of S at p^o_i */
+    for (int a = 0; a < 3; ++a) x[a] = P->center[a] + P->radius * po[a];
+    if (P->jitter) {
+        ustream uj;
+        us_init(&uj, P->seed, k, s, 0, P_FLIGHT);
+        double u0 = us_get(&uj, 0), u1 = us_get(&uj, 1);
+        double rho = 2.0 * P->radius / sqrt((double)P->M) * sqrt(u0);
+        double ang = 2.0 * PI * u1;
+        double t1[3], t2[3];
+        orc_frame(po, t1, t2);
+        for (int a = 0; a < 3; ++a) x[a] += rho * (cos(ang) * t1[a] + sin(ang) * t2[a]);
+    }
+    trace_path(tr, k, s, x, dir, L);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -838,9 +848,9 @@ typedef struct {
 /* Pinhole camera ray through the centre of pixel (x, y), row 0 at the top;
  * front and back hit points on S (tangential rays, with b^2 - c <= 1e-6 R^2,
  * are discarded); nearest and K neighbours of each hit point in its set. */
-static void query_pixel(const orc_params* P, const orc_camera* cam, int32_t W, int32_t H, int32_t K,
-                        int32_t px, int32_t py, pixel_query* q) {
-    double fwd[3], right[3], up[3], d[3];
+/* Unit direction of the pinhole ray through the centre of pixel (px, py). */
+static void camera_dir(const orc_camera* cam, int32_t W, int32_t H, int32_t px, int32_t py, double d[3]) {
+    double fwd[3], right[3], up[3];
     sub3(cam->target, cam->eye, fwd);
     normalize3(fwd);
     cross3(fwd, cam->up, right);
@@ -852,6 +862,12 @@ static void query_pixel(const orc_params* P, const orc_camera* cam, int32_t W, i
     double sy = (1.0 - 2.0 * ((double)py + 0.5) / (double)H) * th;
     for (int a = 0; a < 3; ++a) d[a] = fwd[a] + sx * right[a] + sy * up[a];
     normalize3(d);
+}
+
+static void query_pixel(const orc_params* P, const orc_camera* cam, int32_t W, int32_t H, int32_t K,
+                        int32_t px, int32_t py, pixel_query* q) {
+    double d[3];
+    camera_dir(cam, W, H, px, py, d);
     double oc[3];
     sub3(cam->eye, P->center, oc);
     double b = dot3(d, oc);
@@ -972,6 +988,99 @@ void orc_lookup_adjoint(const orc_params* prm, const orc_camera* cams, int32_t W
                 double* t = d_lf + 3 * (q.ia[a] * prm->N + q.jb[b]);
                 for (int c = 0; c < 3; ++c) t[c] += wab[a * 9 + b] * dimg[3 * p + c];
             }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ground-truth views: the same path tracer along pinhole camera rays         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    tracer tr;
+    const orc_camera* cams; int32_t W, H; const int32_t* pix; int64_t p0, p1; double* rgb;
+} render_job;
+
+static void* render_worker(void* arg) {
+    render_job* jb = (render_job*)arg;
+    const orc_params* P = jb->tr.prm;
+    for (int64_t p = jb->p0; p < jb->p1; ++p) {
+        const int32_t* px = jb->pix + 3 * p;
+        const orc_camera* cam = &jb->cams[px[0]];
+        double d[3], acc[3] = {0.0, 0.0, 0.0};
+        camera_dir(cam, jb->W, jb->H, px[1], px[2], d);
+        /* stream key: the pixel's index in the [view][row][column] image */
+        uint32_t k = (uint32_t)(((int64_t)px[0] * jb->H + px[2]) * jb->W + px[1]);
+        for (int32_t s = 0; s < P->spp; ++s) {
+            double L[3];
+            trace_path(&jb->tr, k, (uint32_t)s, cam->eye, d, L);
+            for (int c = 0; c < 3; ++c) acc[c] += L[c];
+        }
+        for (int c = 0; c < 3; ++c) jb->rgb[3 * p + c] = acc[c] / (double)P->spp;
+    }
+    return NULL;
+}
+
+void orc_render(const orc_volume* vol, const orc_medium* med, const orc_light* light, const orc_params* prm,
+                const orc_camera* cams, int32_t W, int32_t H, const int32_t* pix, int64_t npx, double* rgb,
+                int32_t nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    double* maj = build_grid(vol, med, NULL, prm);
+    render_job* jobs = (render_job*)calloc((size_t)nthreads, sizeof(render_job));
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nthreads);
+    for (int32_t t = 0; t < nthreads; ++t) {
+        tracer_setup(&jobs[t].tr, vol, med, NULL, light, prm, maj);
+        jobs[t].cams = cams;
+        jobs[t].W = W;
+        jobs[t].H = H;
+        jobs[t].pix = pix;
+        jobs[t].p0 = npx * t / nthreads;
+        jobs[t].p1 = npx * (t + 1) / nthreads;
+        jobs[t].rgb = rgb;
+        pthread_create(&th[t], NULL, render_worker, &jobs[t]);
+    }
+    for (int32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(th);
+    free(jobs);
+    free(maj);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mean SSIM (Wang, Bovik, Sheikh, Simoncelli 2004) as defined: windowed     */
+/* means, variances and covariance with the 11 x 11 Gaussian window of sigma  */
+/* 1.5 (sum 1), at every window position inside the image, per channel.      */
+/* ------------------------------------------------------------------------ */
+void orc_ssim(const float* a, const float* b, int32_t n, int32_t W, int32_t H, double data_range, double* out) {
+    double g[11], gs = 0.0;
+    for (int t = 0; t < 11; ++t) {
+        g[t] = exp(-(double)((t - 5) * (t - 5)) / (2.0 * 1.5 * 1.5));
+        gs += g[t];
+    }
+    for (int t = 0; t < 11; ++t) g[t] /= gs;
+    const double c1 = (0.01 * data_range) * (0.01 * data_range);
+    const double c2 = (0.03 * data_range) * (0.03 * data_range);
+    for (int32_t m = 0; m < n; ++m) {
+        const float* A = a + (size_t)m * H * W * 3;
+        const float* B = b + (size_t)m * H * W * 3;
+        double total = 0.0;
+        for (int c = 0; c < 3; ++c)
+            for (int32_t y = 0; y + 10 < H; ++y)
+                for (int32_t x = 0; x + 10 < W; ++x) {
+                    double ma = 0.0, mb = 0.0, aa = 0.0, bb = 0.0, ab = 0.0;
+                    for (int v = 0; v < 11; ++v)
+                        for (int u = 0; u < 11; ++u) {
+                            double w = g[v] * g[u];
+                            size_t o = ((size_t)(y + v) * W + (x + u)) * 3 + c;
+                            double va = A[o], vb = B[o];
+                            ma += w * va;
+                            mb += w * vb;
+                            aa += w * va * va;
+                            bb += w * vb * vb;
+                            ab += w * va * vb;
+                        }
+                    double sa = aa - ma * ma, sb = bb - mb * mb, sab = ab - ma * mb;
+                    total += ((2.0 * ma * mb + c1) * (2.0 * sab + c2)) /
+                             ((ma * ma + mb * mb + c1) * (sa + sb + c2));
+                }
+        out[m] = total / (3.0 * (double)(W - 10) * (double)(H - 10));
     }
 }
 

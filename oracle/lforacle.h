@@ -192,6 +192,27 @@ void orc_lookup_adjoint(const orc_params* prm, const orc_camera* cams,
                         int32_t W, int32_t H, int32_t K, const int32_t* pix,
                         int64_t npx, const double* dimg, double* d_lf);
 
+/* ---- Ground-truth views (the paper's reference images: the path tracer
+ * itself along camera rays) -----------------------------------------------
+ * For npx pixels (view v, x, y) = pix[3p..] of the pinhole views cams[] at
+ * W x H (pixel centres, row 0 at the top), rgb[3p..] = mean over spp path
+ * samples from the eye along the pixel's ray, traced as orc_generate traces
+ * a light-field ray (no origin jitter).  Random-number stream key: the
+ * pixel's index (v H + y) W + x.  Uses spp, max_bounces, g, majorant, grid
+ * and seed of prm.  Pinned by vacuum, Beer-Lambert along camera rays, and
+ * agreement in expectation with light-field rays on the same lines. */
+void orc_render(const orc_volume* vol, const orc_medium* med, const orc_light* light, const orc_params* prm,
+                const orc_camera* cams, int32_t W, int32_t H, const int32_t* pix, int64_t npx, double* rgb,
+                int32_t nthreads);
+
+/* ---- Mean SSIM (Wang et al. 2004), the image index the paper reports ----
+ * out[m] for image pairs a, b ([n][H][W][3] float32): 11 x 11 Gaussian
+ * window of sigma 1.5 normalised to sum 1, C1 = (0.01 range)^2,
+ * C2 = (0.03 range)^2, every window position inside the image, averaged
+ * over positions and channels.  Pinned by SSIM(x, x) = 1, the closed form
+ * for constant images, symmetry, and a separable scipy filter. */
+void orc_ssim(const float* a, const float* b, int32_t n, int32_t W, int32_t H, double data_range, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,8 @@ def lib():
         L.orc_gradient.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, C.c_int32]
         L.orc_lookup.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64, P, P, P, C.c_int32]
         L.orc_lookup_adjoint.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64, P, P]
+        L.orc_render.argtypes = [P, P, P, P, P, C.c_int32, C.c_int32, P, C.c_int64, P, C.c_int32]
+        L.orc_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_double, P]
         _lib = L
     return _lib
 
@@ -325,6 +327,32 @@ def lookup_adjoint(params, cams, width, height, K, pix, dimg) -> np.ndarray:
     d = np.zeros(stored_rows(params) * params.N * 3)
     lib().orc_lookup_adjoint(C.byref(p), cs, width, height, K, _ptr(pix), pix.shape[0], _ptr(dimg), _ptr(d))
     return d
+
+
+def render(scene, cams, width, height, pix, nthreads=None) -> np.ndarray:
+    """Ground-truth RGB [npx, 3] of the listed pixels pix = [(view, x, y), ...]:
+    mean over spp path samples along each pinhole ray."""
+    keep = []
+    pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
+    out = np.zeros((pix.shape[0], 3))
+    v = _vol(scene.volume, keep)
+    m = _med(scene.medium, keep)
+    l = _light(scene.light)
+    p = _params(scene.params)
+    cs = _cams(cams)
+    lib().orc_render(C.byref(v), C.byref(m), C.byref(l), C.byref(p), cs, width, height, _ptr(pix), pix.shape[0],
+                     _ptr(out), nthreads or default_threads())
+    return out
+
+
+def ssim(a, b, data_range=1.0) -> np.ndarray:
+    """Mean SSIM [n] of float32 image pairs [n, H, W, 3]."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    n, H, W, _ = a.shape
+    out = np.zeros(n)
+    lib().orc_ssim(_ptr(a), _ptr(b), n, W, H, data_range, _ptr(out))
+    return out
 
 
 def all_pixels(nviews: int, width: int, height: int) -> np.ndarray:

@@ -25,7 +25,7 @@ import torch
 
 __all__ = [
     "LumiPathError", "Volume", "Medium", "Light", "GenParams", "Camera", "library", "library_path",
-    "points", "generate", "generate_backward", "lookup", "majorant_grid", "lookup_adjoint", "LightFieldFn", "LookupFn",
+    "points", "generate", "generate_backward", "lookup", "majorant_grid", "render_views", "ssim", "lookup_adjoint", "LightFieldFn", "LookupFn",
     "device_scene", "DTYPES",
 ]
 
@@ -96,7 +96,11 @@ def library():
         L.lf_lookup.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 P, P, P, P]
         L.lf_majorant_grid.argtypes = [P, P, P, P, P]
-        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_majorant_grid):
+        L.lf_render_views.argtypes = [P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P,
+                                      C.POINTER(C.c_size_t), P]
+        L.lf_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.POINTER(C.c_size_t), P]
+        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_majorant_grid,
+                  L.lf_render_views, L.lf_ssim):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -306,6 +310,38 @@ def generate(vol: Volume, med: Medium, light: Light, prm: GenParams, dtype: str 
             _ptr(out)]
     ws, sz = _workspace(L.lf_generate, *args)
     _check(L.lf_generate(*args, _ptr(ws), C.byref(sz), _stream()))
+    return out
+
+
+def render_views(vol: Volume, med: Medium, light: Light, prm: GenParams, cams: Sequence[Camera], width: int,
+                 height: int, img: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """lf_render_views: ground-truth images [V, H, W, 3] (float32), prm.spp
+    path samples per pixel along the pinhole rays."""
+    V = len(cams)
+    if img is None:
+        img = torch.empty((V, height, width, 3), dtype=torch.float32, device=vol.data.device)
+    _need(img, V * height * width * 3, torch.float32, "img")
+    L = library()
+    v, m, l, p = vol.c(), med.c(), light.c(), prm.c()
+    cs = _cams(cams)
+    args = [C.byref(v), C.byref(m), C.byref(l), C.byref(p), cs, V, width, height, _ptr(img)]
+    ws, sz = _workspace(L.lf_render_views, *args)
+    _check(L.lf_render_views(*args, _ptr(ws), C.byref(sz), _stream()))
+    return img
+
+
+def ssim(a: torch.Tensor, b: torch.Tensor, data_range: float = 1.0) -> torch.Tensor:
+    """lf_ssim: mean SSIM [n] (float64) of image pairs [n, H, W, 3] (float32)."""
+    if a.shape != b.shape or a.dim() != 4 or a.shape[-1] != 3:
+        raise ValueError("a and b must both be [n, H, W, 3]")
+    a = a.contiguous().float()
+    b = b.contiguous().float()
+    n, H, W, _ = a.shape
+    out = torch.empty(n, dtype=torch.float64, device=a.device)
+    L = library()
+    args = [_ptr(a), _ptr(b), n, W, H, float(data_range), _ptr(out)]
+    ws, sz = _workspace(L.lf_ssim, *args)
+    _check(L.lf_ssim(*args, _ptr(ws), C.byref(sz), _stream()))
     return out
 
 

@@ -300,6 +300,131 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     return LF_OK;
 }
 
+int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_light* light,
+                    const lf_gen_params* params, const lf_camera* cams, int32_t n_views, int32_t W, int32_t H,
+                    float* img, void* ws, size_t* ws_bytes, void* stream) {
+    g_err.clear();
+    int r;
+    if ((r = check_volume(vol)) || (r = check_medium(medium, "")) || (r = check_light(light))) return r;
+    if (!params) return fail(LF_E_ARG, "params is NULL");
+    if (params->spp < 1) return fail(LF_E_ARG, "spp must be >= 1");
+    if (params->max_bounces < 1 || params->max_bounces > 65535)
+        return fail(LF_E_ARG, "max_bounces must be in [1, 65535]");
+    if (!(std::fabs(params->hg_g) < 1.0f)) return fail(LF_E_ARG, "|hg_g| must be < 1");
+    if (!std::isfinite(params->majorant)) return fail(LF_E_ARG, "majorant must be finite");
+    if (params->majorant_grid < 0 || params->majorant_grid > 16)
+        return fail(LF_E_ARG, "majorant_grid must be in [0, 16] (got %d)", params->majorant_grid);
+    if (!cams) return fail(LF_E_ARG, "cams is NULL");
+    if (n_views < 1 || W < 1 || H < 1) return fail(LF_E_ARG, "n_views, W and H must be >= 1");
+    if ((unsigned long long)n_views * (unsigned long long)W * (unsigned long long)H >= (1ull << 32))
+        return fail(LF_E_RANGE, "n_views * W * H must be < 2^32");
+    if (!img) return fail(LF_E_ARG, "img is NULL");
+    std::vector<lp::ViewCam> vc((size_t)n_views);
+    for (int v = 0; v < n_views; ++v) {
+        const lf_camera& c = cams[v];
+        double f[3], u[3], rt[3], up[3];
+        for (int a = 0; a < 3; ++a) {
+            f[a] = (double)c.target[a] - c.eye[a];
+            u[a] = c.up[a];
+        }
+        const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        if (!(c.vfov > 0.0f && c.vfov < 3.14159f) || !(fl > 0.0) || !finite3(c.eye))
+            return fail(LF_E_ARG, "camera %d: bad eye, field of view or target", v);
+        for (int a = 0; a < 3; ++a) f[a] /= fl;
+        rt[0] = f[1] * u[2] - f[2] * u[1];
+        rt[1] = f[2] * u[0] - f[0] * u[2];
+        rt[2] = f[0] * u[1] - f[1] * u[0];
+        const double rl = std::sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+        if (!(rl > 1e-9)) return fail(LF_E_ARG, "camera %d: up is parallel to the view direction", v);
+        for (int a = 0; a < 3; ++a) rt[a] /= rl;
+        up[0] = rt[1] * f[2] - rt[2] * f[1];
+        up[1] = rt[2] * f[0] - rt[0] * f[2];
+        up[2] = rt[0] * f[1] - rt[1] * f[0];
+        const double th = std::tan(0.5 * c.vfov);
+        lp::ViewCam& g = vc[v];
+        for (int a = 0; a < 3; ++a) {
+            g.eye[a] = c.eye[a];
+            g.fwd[a] = (float)f[a];
+            g.right[a] = (float)rt[a];
+            g.up[a] = (float)up[a];
+        }
+        g.sx = (float)(th * (double)W / (double)H);
+        g.sy = (float)th;
+    }
+    // the tracer set-up of lf_generate with a one-point ray set, then the views
+    lf_gen_params p1 = *params;
+    p1.M = p1.N = 1;
+    p1.origin_rows = 0;
+    p1.row_begin = 0;
+    p1.row_end = 1;
+    p1.jitter = 0;
+    const size_t views_bytes = align256(sizeof(lp::ViewCam) * (size_t)n_views);
+    const size_t need = gen_order_bytes(&p1) + views_bytes + brick4_bytes(vol);
+    r = check_workspace(ws, ws_bytes, need);
+    if (r == 1) {
+        *ws_bytes = need;
+        return LF_OK;
+    }
+    if (r) return r;
+    lp::TraceParams T;
+    pack_trace(T, vol, medium, nullptr, light, &p1);
+    T.out = img;
+    T.dtype = LF_F32;
+    char* w = (char*)ws;
+    lp::ViewCam* dv = (lp::ViewCam*)(w + gen_order_bytes(&p1));
+    T.vol = w + gen_order_bytes(&p1) + views_bytes;
+    T.views = dv;
+    T.nviews = n_views;
+    T.W = W;
+    T.H = H;
+    T.vtx = (W + 7) / 8;
+    T.vtiles = T.vtx * ((H + 7) / 8);
+    hipStream_t s = (hipStream_t)stream;
+    // the host array is staged by the runtime before the call returns
+    hipError_t e = hipMemcpyAsync(dv, vc.data(), sizeof(lp::ViewCam) * (size_t)n_views, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
+    if (e == hipSuccess) e = setup_tracking(T, vol, medium, &p1, w, s);
+    if (e == hipSuccess) e = lp::launch_generate_wave(T, vol->type, lp::kFwd, s);
+    if (e != hipSuccess) return hip_fail(e, "lf_render_views");
+    return LF_OK;
+}
+
+int lf_ssim(const float* a, const float* b, int32_t n_images, int32_t W, int32_t H, float data_range, double* out,
+            void* ws, size_t* ws_bytes, void* stream) {
+    g_err.clear();
+    if (!a || !b || !out) return fail(LF_E_ARG, "a, b and out must be non-NULL");
+    if (n_images < 1 || n_images > 21845) return fail(LF_E_ARG, "n_images must be in [1, 21845]");
+    if (W < 11 || H < 11) return fail(LF_E_ARG, "images must be at least 11 x 11 (the window)");
+    if ((long long)W * H > (1ll << 30)) return fail(LF_E_RANGE, "image too large");
+    if (!(data_range > 0.0f) || !std::isfinite(data_range)) return fail(LF_E_ARG, "data_range must be > 0");
+    const size_t need = align256(sizeof(double) * lp::ssim_partial_count(n_images, W, H));
+    int r = check_workspace(ws, ws_bytes, need);
+    if (r == 1) {
+        *ws_bytes = need;
+        return LF_OK;
+    }
+    if (r) return r;
+    lp::SsimParams P;
+    P.a = a;
+    P.b = b;
+    P.W = W;
+    P.H = H;
+    double g[11], sum = 0.0;
+    for (int t = 0; t < 11; ++t) {
+        g[t] = std::exp(-(double)((t - 5) * (t - 5)) / (2.0 * 1.5 * 1.5));
+        sum += g[t];
+    }
+    for (int t = 0; t < 11; ++t) P.w[t] = (float)(g[t] / sum);
+    P.c1 = (float)((0.01 * data_range) * (0.01 * data_range));
+    P.c2 = (float)((0.03 * data_range) * (0.03 * data_range));
+    P.partial = (double*)ws;
+    P.out = out;
+    hipError_t e = lp::launch_ssim(P, n_images, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lf_ssim");
+    return LF_OK;
+}
+
 int lf_majorant_grid(const lf_volume* vol, const lf_medium* sample, const lf_gen_params* params, float* out,
                      void* stream) {
     g_err.clear();

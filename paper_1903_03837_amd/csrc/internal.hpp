@@ -33,6 +33,20 @@ struct LookupParams {
     ViewGeom v[kMaxViewsPerLaunch];
 };
 
+// Mean SSIM of image pairs [n][H][W][3] (metrics.hip).
+struct SsimParams {
+    const float* a;
+    const float* b;
+    int32_t W, H;
+    float w[11];            // normalised 1-D Gaussian window, sigma 1.5
+    float c1, c2;           // (0.01 L)^2, (0.03 L)^2
+    double* partial;        // one slot per workgroup
+    double* out;            // [n] mean SSIM
+};
+
+hipError_t launch_ssim(const SsimParams& P, int n_images, hipStream_t s);
+size_t ssim_partial_count(int n_images, int W, int H);
+
 hipError_t launch_points(int n, float* xyz, const float* query, long long nq, int K, int* idx, float* w,
                          hipStream_t s);
 hipError_t launch_brick4(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst, hipStream_t s);

@@ -39,6 +39,13 @@ enum { kPurFlight = 1, kPurVertex = 2 };
 // or fully blocked (shadow), so no lane can spin.
 constexpr uint32_t kMaxBlocks = 1u << 19;
 
+// Pinhole view for ground-truth rendering: eye, orthonormal basis and the
+// half-extents tan(vfov / 2) * aspect, tan(vfov / 2) of the image plane.
+struct ViewCam {
+    float eye[3], fwd[3], right[3], up[3];
+    float sx, sy;
+};
+
 struct TraceParams {
     // volume: the library's 4^3-brick copy (bricks x-fastest, voxels
     // x-fastest inside a brick; 4 x 4 x 4 u16 voxels fill one 128-byte line)
@@ -86,6 +93,11 @@ struct TraceParams {
     // majorant grid: grid_n^3 cell majorants (x fastest) over the volume box;
     // grid_n = 1 with maj = sigbar is the global majorant
     int32_t grid_n, nz;
+    // ground-truth views (views != nullptr): camera rays instead of the SF ray
+    // set, 8 x 8 pixel tiles, stream key = (view * H + y) * W + x
+    const ViewCam* views;
+    int32_t nviews, W, H;
+    int32_t vtx, vtiles;             // tiles per image row, tiles per view
     float gcell[3];                  // cells per world unit
     float gcw[3];                    // cell width
     const float* maj;

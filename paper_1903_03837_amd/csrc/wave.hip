@@ -65,7 +65,9 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     const int rows = P.row_end - P.row_begin;
     const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
     const long long nlist = MODE == kGrad ? (long long)*P.ray_count : 0;
-    const long long ntiles = MODE == kGrad ? (nlist + 63) / 64 : (long long)tiles_i * tiles_j;
+    const long long ntiles = MODE == kGrad ? (nlist + 63) / 64
+                             : P.views   ? (long long)P.nviews * P.vtiles
+                                         : (long long)tiles_i * tiles_j;
     const int home = blockIdx.x % kParts;
     const float inv_spp = 1.0f / (float)P.spp;
     const float invM = 1.0f / (float)P.M, invN = 1.0f / (float)P.N;
@@ -134,6 +136,27 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         adj = mk3(a[0] * inv_spp, a[1] * inv_spp, a[2] * inv_spp);
                         pass = 0;
                     }
+                } else if (P.views) {
+                    // pixel of an 8 x 8 tile of a view: the ray from the eye through its centre
+                    const uint32_t t = (uint32_t)(q >> 6);
+                    const uint32_t v = t / (uint32_t)P.vtiles, rem = t - v * (uint32_t)P.vtiles;
+                    const uint32_t ty = rem / (uint32_t)P.vtx, tx = rem - ty * (uint32_t)P.vtx;
+                    const int py = (int)ty * 8 + (int)((q >> 3) & 7), px = (int)tx * 8 + (int)(q & 7);
+                    if (py < P.H && px < P.W) {
+                        const ViewCam& cam = P.views[v];
+                        const float ndx = (2.0f * ((float)px + 0.5f) / (float)P.W - 1.0f) * cam.sx;
+                        const float ndy = (1.0f - 2.0f * ((float)py + 0.5f) / (float)P.H) * cam.sy;
+                        k = (v * (uint32_t)P.H + (uint32_t)py) * (uint32_t)P.W + (uint32_t)px;
+                        po = mk3(cam.eye[0], cam.eye[1], cam.eye[2]);
+                        d0 = normalize(mk3(cam.fwd[0], cam.fwd[1], cam.fwd[2]) +
+                                       mk3(cam.right[0], cam.right[1], cam.right[2]) * ndx +
+                                       mk3(cam.up[0], cam.up[1], cam.up[2]) * ndy);
+                        acc = mk3(0.0f, 0.0f, 0.0f);
+                        s = 0;
+                        b = 0;
+                        blk = 0;
+                        mode = kStart;
+                    }
                 } else {
                     int ti, tj;
                     tile_coords(q >> 6, tiles_i, tiles_j, ti, tj);
@@ -174,8 +197,9 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
 
         if (mode == kStart) {
             cnt.samples++;
-            x = O + po * P.R;
-            if (P.jitter) {
+            // light-field ray: origin on S (jittered); view ray: the eye
+            x = P.views ? po : O + po * P.R;
+            if (P.jitter && !P.views) {
                 const float rho = P.jit_rad * sqrtf(u01(r.x));
                 float sa, ca;
                 sincospif(2.0f * u01(r.y), &sa, &ca);
@@ -523,7 +547,7 @@ hipError_t launch_active_rays(const TraceParams& P, hipStream_t s) {
 template <int VT, int MODE>
 static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
-    const long long ntiles = ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
+    const long long ntiles = P.views ? (long long)P.nviews * P.vtiles : ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
     if (ntiles <= 0) return hipSuccess;
     const size_t ncell = (size_t)P.grid_n * P.grid_n * P.grid_n;
     const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
