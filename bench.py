@@ -11,6 +11,7 @@ ray, 8 bounces, HG g = 0.3, area light):
 on stdout; progress on stderr.  Inputs are seeded synthetic data (lfsynth).
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -183,6 +184,28 @@ def main():
     err16 = (f16 - f32).abs().sum().item() / denom
     errb16 = (b16 - f32).abs().sum().item() / denom
 
+    # image quality against path-traced views (not part of the timed step):
+    # 4 of the views at 480 x 270, ground truth at 256 spp
+    qv, qw, qh, qspp = 4, 480, 270, 256
+    qcams = cams[:qv]
+    gt_prm = dataclasses.replace(prm, spp=qspp)
+    gt = lp.render_views(vol, med, light, gt_prm, qcams, qw, qh)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lp.render_views(vol, med, light, gt_prm, qcams, qw, qh, img=gt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    render_ms = e0.elapsed_time(e1)
+    gmax = float(gt.max())
+    quality = {"views": qv, "width": qw, "height": qh, "ground_truth_spp": qspp,
+               "render_ms": render_ms, "render_samples_per_s": qv * qw * qh * qspp / (render_ms / 1e3)}
+    for kk in (1, K):
+        v_img = lp.lookup(lf, prm, qcams, qw, qh, kk)
+        quality[f"ssim_K{kk}"] = float(lp.ssim(v_img, gt, data_range=gmax).mean())
+        quality[f"rel_l1_K{kk}"] = float((v_img - gt).abs().sum() / gt.abs().sum())
+    log("bench: light-field views vs ground truth " + json.dumps(quality))
+
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 4
         a_ = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
@@ -233,6 +256,7 @@ def main():
         "adjoint_forward_ratio": legs["generate_backward"] / legs["generate"],
         "fp16_vs_fp32_rel_err": err16,
         "bf16_vs_fp32_rel_err": errb16,
+        "quality_vs_ground_truth": quality,
         "collisions_per_sample": tent / samples,
         "cell_steps_per_sample": cells / samples,
         "kernel_hash": khash,
