@@ -68,6 +68,8 @@ class Params:
     g: float = 0.0
     majorant: float = 0.0     # <= 0: 1.25 * scale * max alpha
     grid: int = 0             # majorant grid cells per axis (0: one global majorant)
+    surface: int = 0          # 1: isosurface variant at raw value iso
+    iso: float = 0.0
     seed: int = 0
     jitter: int = 1
     origin_rows: int = 0      # 0: all M origins; M // 2: upper hemisphere only

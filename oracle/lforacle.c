@@ -528,10 +528,155 @@ static int next_tentative(const piece* pc, int np, double* t, double tau, double
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Isosurface variant                                                          */
+/* ------------------------------------------------------------------------ */
+static double iso_field(const orc_volume* vol, const orc_params* P, const double x[3], const double d[3], double t) {
+    double y[3] = {x[0] + t * d[0], x[1] + t * d[1], x[2] + t * d[2]};
+    return sample_volume(vol, y) - P->iso;
+}
+
+static double half_voxel(const orc_volume* vol) {
+    double h = INFINITY;
+    int64_t n[3] = {vol->nx, vol->ny, vol->nz};
+    for (int a = 0; a < 3; ++a) {
+        double e = (vol->box_max[a] - vol->box_min[a]) / (double)n[a];
+        if (e < h) h = e;
+    }
+    return 0.5 * h;
+}
+
+int32_t orc_surface_hit(const orc_volume* vol, const orc_params* prm, const double x[3], const double d[3],
+                        double t0, double t1, double* thit) {
+    const double h = half_voxel(vol);
+    double ta = t0, fa = iso_field(vol, prm, x, d, t0);
+    for (int64_t m = 1;; ++m) {
+        double tb = t0 + (double)m * h;
+        if (tb > t1) tb = t1;
+        double fb = iso_field(vol, prm, x, d, tb);
+        if ((fa >= 0.0) != (fb >= 0.0)) {
+            double lo = ta, hi = tb, flo = fa;
+            for (int it = 0; it < 40; ++it) {
+                double mid = 0.5 * (lo + hi), fm = iso_field(vol, prm, x, d, mid);
+                if ((fm >= 0.0) == (flo >= 0.0)) { lo = mid; flo = fm; }
+                else hi = mid;
+            }
+            *thit = lo;  /* the bracket end on the ray's starting side */
+            return 1;
+        }
+        if (tb >= t1) return 0;
+        ta = tb;
+        fa = fb;
+    }
+}
+
+/* Unit normal of the surface at y: central differences of f over a quarter
+ * voxel, turned to face the incoming direction d (-d where f is flat). */
+static void surface_normal(const orc_volume* vol, const double y[3], const double d[3], double n[3]) {
+    const double e = 0.5 * half_voxel(vol);
+    for (int a = 0; a < 3; ++a) {
+        double yp[3] = {y[0], y[1], y[2]}, ym[3] = {y[0], y[1], y[2]};
+        yp[a] += e;
+        ym[a] -= e;
+        n[a] = (sample_volume(vol, yp) - sample_volume(vol, ym)) / (2.0 * e);
+    }
+    double l = norm3(n);
+    if (!(l > 0.0)) {
+        for (int a = 0; a < 3; ++a) n[a] = -d[a];
+        return;
+    }
+    for (int a = 0; a < 3; ++a) n[a] /= l;
+    if (dot3(n, d) > 0.0)
+        for (int a = 0; a < 3; ++a) n[a] = -n[a];
+}
+
+/* Surface path: at each vertex the Lambertian BRDF rho / pi with rho the
+ * LUT colour at the isovalue (clamped to [0, 1]); next-event estimation
+ * towards the light with a visibility ray; a cosine-weighted bounce
+ * (weight rho).  Vertex stream b: pair 0 light sample, pair 1 bounce
+ * direction.  The vertex is the bracket end on the incoming side, so new
+ * rays start on the side the path came from, with no offset. */
+static void trace_surface_path(tracer* tr, uint32_t k, uint32_t s, const double x0[3], const double d0[3],
+                               double L[3]) {
+    const orc_params* P = tr->prm;
+    const orc_light* lt = tr->light;
+    const orc_volume* vol = tr->vol;
+    const double* bmin = vol->box_min;
+    const double* bmax = vol->box_max;
+    double x[3] = {x0[0], x0[1], x0[2]}, dir[3] = {d0[0], d0[1], d0[2]};
+    double T[3] = {1.0, 1.0, 1.0};
+    double rho[3];
+    {
+        tfsample ts = classify(vol, tr->eval, P->iso);
+        for (int c = 0; c < 3; ++c) rho[c] = clamp01(ts.rgb[c]);
+    }
+    L[0] = L[1] = L[2] = 0.0;
+    tr->stats[3] += 1.0;
+    for (int32_t b = 0; b < P->max_bounces; ++b) {
+        double tn, tf, th;
+        if (!clip_box(x, dir, bmin, bmax, &tn, &tf) || !orc_surface_hit(vol, P, x, dir, tn, tf, &th)) {
+            for (int c = 0; c < 3; ++c) L[c] += T[c] * lt->env[c];
+            return;
+        }
+        tr->stats[2] += 1.0;
+        double y[3], n[3];
+        for (int a = 0; a < 3; ++a) y[a] = x[a] + th * dir[a];
+        surface_normal(vol, y, dir, n);
+        ustream uv;
+        us_init(&uv, P->seed, k, s, (uint32_t)b, P_VERTEX);
+        double ul0 = us_get(&uv, 0), ul1 = us_get(&uv, 1), up0 = us_get(&uv, 2), up1 = us_get(&uv, 3);
+        const double* org = y;
+        if (tr->light_on) {
+            double om[3], Le[3], tend = 0.0;
+            if (lt->kind == ORC_LIGHT_DIRECTIONAL) {
+                om[0] = lt->dir[0]; om[1] = lt->dir[1]; om[2] = lt->dir[2];
+                for (int c = 0; c < 3; ++c) Le[c] = lt->radiance[c];
+                double a0, a1;
+                if (clip_box(org, om, bmin, bmax, &a0, &a1)) tend = a1;
+            } else {
+                double yl[3], v[3], nl[3];
+                for (int a = 0; a < 3; ++a) yl[a] = lt->corner[a] + ul0 * lt->e1[a] + ul1 * lt->e2[a];
+                sub3(yl, org, v);
+                double dist = norm3(v);
+                for (int a = 0; a < 3; ++a) om[a] = v[a] / dist;
+                cross3(lt->e1, lt->e2, nl);
+                double area = norm3(nl);
+                for (int a = 0; a < 3; ++a) nl[a] /= area;
+                double cl = -dot3(nl, om);
+                if (cl < 0.0) cl = 0.0;
+                for (int c = 0; c < 3; ++c) Le[c] = lt->radiance[c] * cl * area / (dist * dist);
+                double a0, a1;
+                tend = dist;
+                if (clip_box(org, om, bmin, bmax, &a0, &a1)) { if (a1 < tend) tend = a1; }
+                else tend = 0.0;
+            }
+            double cosl = dot3(n, om);
+            double tv;
+            if (cosl > 0.0 && !(tend > 0.0 && orc_surface_hit(vol, P, org, om, 0.0, tend, &tv)))
+                for (int c = 0; c < 3; ++c) L[c] += T[c] * rho[c] / PI * cosl * Le[c];
+        }
+        if (b == P->max_bounces - 1) return;
+        /* cosine-weighted direction about n: weight rho */
+        double r = sqrt(up0), ph = 2.0 * PI * up1;
+        double t1[3], t2[3];
+        orc_frame(n, t1, t2);
+        double cz = sqrt(1.0 - up0 > 0.0 ? 1.0 - up0 : 0.0);
+        for (int a = 0; a < 3; ++a) dir[a] = r * cos(ph) * t1[a] + r * sin(ph) * t2[a] + cz * n[a];
+        normalize3(dir);
+        for (int c = 0; c < 3; ++c) T[c] *= rho[c];
+        if (T[0] == 0.0 && T[1] == 0.0 && T[2] == 0.0) return;
+        for (int a = 0; a < 3; ++a) x[a] = y[a];
+    }
+}
+
 /* One path sample of stream key k, sample s, from x0 along the unit d0: the
  * path tracer of Sec. 2 (volumetric reading) with the random-number layout
  * described above. */
 static void trace_path(tracer* tr, uint32_t k, uint32_t s, const double x0[3], const double d0[3], double L[3]) {
+    if (tr->prm->surface) {
+        trace_surface_path(tr, k, s, x0, d0, L);
+        return;
+    }
     const orc_params* P = tr->prm;
     const orc_light* lt = tr->light;
     const double* bmin = tr->vol->box_min;

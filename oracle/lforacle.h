@@ -60,6 +60,10 @@ typedef struct {
     int32_t jitter;         /* 1: jitter ray origins on the disk of area 4 pi R^2 / M */
     int32_t grid;           /* majorant grid: G cells per axis (0: one global
                                majorant); ignored when majorant > 0 */
+    int32_t surface;        /* 1: isosurface variant (the volume's trilinear
+                               field at raw value iso is an opaque Lambertian
+                               surface); 0: participating medium */
+    double iso;             /* isovalue of the surface variant (raw units) */
     int64_t origin_rows;    /* origins i < origin_rows are stored (0: all M); the
                                light field is [origin_rows][N][3] (Sec. 3 keeps the
                                upper hemisphere, origin_rows = M / 2) */
@@ -124,6 +128,19 @@ double orc_hg_phase(double g, double mu);
 double orc_hg_sample_mu(double g, double u);
 void orc_frame(const double n[3], double t1[3], double t2[3]);
 
+/* ---- Isosurface variant (the paper renders segmented surfaces) ----------
+ * Surface: where the trilinear raw field f crosses prm->iso.  The first
+ * crossing along x + t d in [t0, t1): f - iso is sampled at t0 + m h
+ * (m = 0, 1, ...; the last sample at t1), h = half the smallest voxel
+ * extent; the first pair of consecutive samples whose signs differ (a zero
+ * counts as positive) is bisected 40 times, and the end of the final
+ * bracket on the starting side is returned (so a path continues on the side
+ * it came from).
+ * Returns 0 when no pair changes sign.  Pinned by a sphere of a radial
+ * field (analytic hit distance) and by exact white-furnace energy. */
+int32_t orc_surface_hit(const orc_volume* vol, const orc_params* prm, const double x[3], const double d[3],
+                        double t0, double t1, double* thit);
+
 /* ---- Majorant: params majorant if > 0 else 1.25 * scale * max alpha ---- */
 double orc_majorant(const orc_medium* sample, const orc_params* prm);
 
@@ -153,7 +170,9 @@ void orc_sigma_at(const orc_volume* vol, const orc_medium* med, const double* pt
  * over spp samples to out[3*r .. 3*r+2].  `sample` may equal `eval`; when it
  * differs, collisions are decided with `sample` and importance-weighted to
  * `eval` (frozen sampling).  With prm->grid > 0 (and no fixed majorant)
- * both trackings use the majorant grid above.  Pinned by Beer-Lambert,
+ * both trackings use the majorant grid above.  With prm->surface the path
+ * runs on the isosurface instead (see orc_surface_hit; frozen sampling and
+ * gradients do not apply).  Pinned by Beer-Lambert,
  * white furnace, vacuum, linearity and symmetry checks, and, for the grid,
  * by quadrature of heterogeneous transmittance and agreement in expectation
  * with the global majorant.  stats (may be NULL) receives

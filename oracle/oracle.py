@@ -48,7 +48,7 @@ class _Params(C.Structure):
     _fields_ = [("M", C.c_int64), ("N", C.c_int64), ("center", C.c_double * 3), ("radius", C.c_double),
                 ("spp", C.c_int32), ("max_bounces", C.c_int32), ("g", C.c_double),
                 ("majorant", C.c_double), ("seed", C.c_uint64), ("jitter", C.c_int32),
-                ("grid", C.c_int32), ("origin_rows", C.c_int64)]
+                ("grid", C.c_int32), ("surface", C.c_int32), ("iso", C.c_double), ("origin_rows", C.c_int64)]
 
 
 class _Camera(C.Structure):
@@ -95,6 +95,8 @@ def lib():
         L.orc_lookup_adjoint.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64, P, P]
         L.orc_render.argtypes = [P, P, P, P, P, C.c_int32, C.c_int32, P, C.c_int64, P, C.c_int32]
         L.orc_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_double, P]
+        L.orc_surface_hit.argtypes = [P, P, P, P, C.c_double, C.c_double, P]
+        L.orc_surface_hit.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -155,6 +157,8 @@ def _params(p):
     s.seed = p.seed
     s.jitter = p.jitter
     s.grid = getattr(p, "grid", 0)
+    s.surface = getattr(p, "surface", 0)
+    s.iso = getattr(p, "iso", 0.0)
     s.origin_rows = getattr(p, "origin_rows", 0)
     return s
 
@@ -343,6 +347,18 @@ def render(scene, cams, width, height, pix, nthreads=None) -> np.ndarray:
     lib().orc_render(C.byref(v), C.byref(m), C.byref(l), C.byref(p), cs, width, height, _ptr(pix), pix.shape[0],
                      _ptr(out), nthreads or default_threads())
     return out
+
+
+def surface_hit(volume, params, x, d, t0, t1):
+    """First isosurface crossing along x + t d in [t0, t1): t, or None."""
+    keep = []
+    v = _vol(volume, keep)
+    p = _params(params)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    th = C.c_double()
+    ok = lib().orc_surface_hit(C.byref(v), C.byref(p), _ptr(x), _ptr(d), t0, t1, C.byref(th))
+    return th.value if ok else None
 
 
 def ssim(a, b, data_range=1.0) -> np.ndarray:
