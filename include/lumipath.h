@@ -111,7 +111,19 @@ typedef struct {
  * generated (row_end <= 0: origin_rows); results do not depend on this
  * split.  stats: NULL or device uint64[5] incremented by [tentative
  * collisions, shadow-ray steps, real collisions, path samples, majorant-cell
- * steps]. */
+ * steps].
+ * surface = 1 selects the isosurface variant (the paper renders segmented
+ * surfaces): the surface is where the trilinear raw field crosses iso.  Its
+ * first crossing along a segment is found by sampling the field every half
+ * voxel from the segment start and bisecting the first pair of samples of
+ * different sign; the vertex is the bracket end on the incoming side.  The
+ * surface is a Lambertian reflector of albedo = the LUT colour at iso
+ * (clamped to [0, 1]; the density scale and alpha are unused) with
+ * next-event estimation (vertex stream pair 0, visibility by the same march)
+ * and cosine-weighted bounces (pair 1); normals are central differences over
+ * a quarter voxel.  The majorant grid size (8 when 0) sets the cells whose
+ * raw ranges let the march skip fetches.  Frozen sampling and
+ * lf_generate_backward are not available in this variant (LF_E_UNSUPPORTED). */
 typedef struct {
     int32_t M, N;
     float center[3];
@@ -125,6 +137,8 @@ typedef struct {
     int32_t origin_rows;    /* stored origin rows: 0 = M; M/2 keeps the upper hemisphere */
     int64_t row_begin, row_end;
     uint64_t* stats;
+    int32_t surface;        /* 1: isosurface variant at raw value iso */
+    float iso;
 } lf_gen_params;
 
 /* Pinhole view (host array): pixel (x, y) looks through its centre, row 0 at

@@ -65,7 +65,8 @@ class _GenParams(C.Structure):
                 ("spp", C.c_int32), ("max_bounces", C.c_int32), ("hg_g", C.c_float), ("majorant", C.c_float),
                 ("majorant_grid", C.c_int32),
                 ("seed", C.c_uint64), ("jitter", C.c_int32), ("origin_rows", C.c_int32),
-                ("row_begin", C.c_int64), ("row_end", C.c_int64), ("stats", C.c_void_p)]
+                ("row_begin", C.c_int64), ("row_end", C.c_int64), ("stats", C.c_void_p),
+                ("surface", C.c_int32), ("iso", C.c_float)]
 
 
 class _Camera(C.Structure):
@@ -208,6 +209,8 @@ class GenParams:
     row_end: int = 0
     origin_rows: int = 0                     # 0: all M origins; M // 2: upper hemisphere
     grid: int = 0                            # majorant grid cells per axis (0: one global majorant)
+    surface: int = 0                         # 1: isosurface variant at raw value iso
+    iso: float = 0.0
 
     @property
     def rows(self) -> int:
@@ -221,6 +224,7 @@ class GenParams:
         s.spp, s.max_bounces = self.spp, self.max_bounces
         s.hg_g, s.majorant = self.g, self.majorant
         s.majorant_grid = self.grid
+        s.surface, s.iso = self.surface, self.iso
         s.seed = self.seed
         s.jitter = self.jitter
         s.origin_rows = self.origin_rows
@@ -267,7 +271,8 @@ def device_scene(scene, device="cuda"):
     p = scene.params
     prm = GenParams(int(p.M), int(p.N), tuple(p.center), float(p.radius), int(p.spp), int(p.max_bounces),
                     float(p.g), float(p.majorant), int(p.seed), int(p.jitter),
-                    origin_rows=int(getattr(p, "origin_rows", 0)), grid=int(getattr(p, "grid", 0)))
+                    origin_rows=int(getattr(p, "origin_rows", 0)), grid=int(getattr(p, "grid", 0)),
+                    surface=int(getattr(p, "surface", 0)), iso=float(getattr(p, "iso", 0.0)))
     cams = [Camera(c.eye, c.target, c.up, c.vfov) for c in getattr(scene, "cams", [])]
     return vol, med, light, prm, cams
 

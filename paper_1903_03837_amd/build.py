@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblumipath.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "generate.hip", "lookup.hip", "wave.hip", "metrics.hip"]
+SOURCES = ["api.cpp", "generate.hip", "lookup.hip", "wave.hip", "metrics.hip", "surface.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

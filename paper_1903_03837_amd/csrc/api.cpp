@@ -76,6 +76,8 @@ int check_params(const lf_gen_params* p, bool need_rays) {
     if (!std::isfinite(p->majorant)) return fail(LF_E_ARG, "majorant must be finite");
     if (p->majorant_grid < 0 || p->majorant_grid > 16)
         return fail(LF_E_ARG, "majorant_grid must be in [0, 16] (got %d)", p->majorant_grid);
+    if (p->surface != 0 && p->surface != 1) return fail(LF_E_ARG, "surface must be 0 or 1");
+    if (!std::isfinite(p->iso)) return fail(LF_E_ARG, "iso must be finite");
     const long long rows = p->origin_rows > 0 ? p->origin_rows : p->M;
     const long long re = p->row_end <= 0 ? rows : p->row_end;
     if (p->row_begin < 0 || p->row_begin > re || re > rows)
@@ -202,6 +204,48 @@ void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, cons
         T.gcw[a] = (float)(ext / T.grid_n);
     }
     T.nz = v->nz;
+    T.surface = p->surface;
+    T.iso = p->iso;
+    double hv = 1e300;
+    for (int a = 0; a < 3; ++a) hv = std::min(hv, ((double)v->box_max[a] - (double)v->box_min[a]) / n[a]);
+    T.half_voxel = (float)(0.5 * hv);
+}
+
+// Isosurface variant: cells of the raw-range grid (the majorant grid size,
+// 8 when none is set) and their bytes in the workspace.
+int surface_cells(const lf_gen_params* p) { return p->majorant_grid > 0 ? p->majorant_grid : 8; }
+size_t surface_range_bytes(const lf_gen_params* p) {
+    if (!p->surface) return 0;
+    const size_t G = (size_t)surface_cells(p);
+    return align256(8 * G * G * G);
+}
+
+// Set-up and launch of the isosurface variant; `range` is its workspace.
+hipError_t run_surface(lp::TraceParams& T, const lf_volume* vol, const lf_medium* m, const lf_gen_params* p,
+                       char* w, float* range, hipStream_t s) {
+    float* sig = (float*)w;
+    unsigned int* ctr = (unsigned int*)(w + 64);
+    int32_t* perm_o = (int32_t*)(w + 256);
+    int32_t* perm_d = (int32_t*)(w + 256 + align256(4 * (size_t)(T.row_end - T.row_begin)));
+    T.sigbar = sig;
+    T.tile_ctr = ctr;
+    T.perm_o = perm_o;
+    T.perm_d = perm_d;
+    const int G = surface_cells(p);
+    T.grid_n = G;
+    for (int a = 0; a < 3; ++a) {
+        const double ext = (double)vol->box_max[a] - (double)vol->box_min[a];
+        T.gcell[a] = (float)(G / ext);
+        T.gcw[a] = (float)(ext / G);
+    }
+    T.srange = range;
+    hipError_t e = lp::launch_wave_setup(T, m->lut, m->lut_size, m->density_scale, p->majorant, sig, ctr, perm_o,
+                                         perm_d, s);
+    if (e == hipSuccess)
+        e = lp::launch_majorant_grid(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, G, m->lut,
+                                     m->lut_size, m->density_scale, vol->vmin, vol->vmax, nullptr, range, s);
+    if (e == hipSuccess) e = lp::launch_surface(T, vol->type, s);
+    return e;
 }
 
 // Majorant set-up shared by both entry points: the global majorant, the tile
@@ -224,7 +268,7 @@ hipError_t setup_tracking(lp::TraceParams& T, const lf_volume* vol, const lf_med
         float* cells = (float*)(w + gen_perm_bytes(p));
         T.maj = cells;
         e = lp::launch_majorant_grid(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, T.grid_n, sm->lut,
-                                     sm->lut_size, sm->density_scale, vol->vmin, vol->vmax, cells, s);
+                                     sm->lut_size, sm->density_scale, vol->vmin, vol->vmax, cells, nullptr, s);
     }
     return e;
 }
@@ -276,7 +320,9 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     }
     if (dtype < LF_F32 || dtype > LF_BF16) return fail(LF_E_ARG, "unknown light-field dtype %d", dtype);
     if (!lf_out) return fail(LF_E_ARG, "lf_out is NULL");
-    const size_t need = gen_order_bytes(params) + brick4_bytes(vol);
+    if (params->surface && sample && sample != eval)
+        return fail(LF_E_UNSUPPORTED, "frozen sampling does not apply to the isosurface variant");
+    const size_t need = gen_order_bytes(params) + brick4_bytes(vol) + surface_range_bytes(params);
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -292,6 +338,12 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     const lf_medium* sm = sample ? sample : eval;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
+    if (params->surface) {
+        if (e == hipSuccess)
+            e = run_surface(T, vol, eval, params, w, (float*)(w + gen_order_bytes(params) + brick4_bytes(vol)), s);
+        if (e != hipSuccess) return hip_fail(e, "lf_generate (isosurface)");
+        return LF_OK;
+    }
     if (e == hipSuccess) e = setup_tracking(T, vol, sm, params, w, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate (set-up)");
     const int mode = (sample && sample != eval) ? lp::kFrozen : lp::kFwd;
@@ -314,6 +366,8 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
     if (!std::isfinite(params->majorant)) return fail(LF_E_ARG, "majorant must be finite");
     if (params->majorant_grid < 0 || params->majorant_grid > 16)
         return fail(LF_E_ARG, "majorant_grid must be in [0, 16] (got %d)", params->majorant_grid);
+    if (params->surface != 0 && params->surface != 1) return fail(LF_E_ARG, "surface must be 0 or 1");
+    if (!std::isfinite(params->iso)) return fail(LF_E_ARG, "iso must be finite");
     if (!cams) return fail(LF_E_ARG, "cams is NULL");
     if (n_views < 1 || W < 1 || H < 1) return fail(LF_E_ARG, "n_views, W and H must be >= 1");
     if ((unsigned long long)n_views * (unsigned long long)W * (unsigned long long)H >= (1ull << 32))
@@ -359,7 +413,7 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
     p1.row_end = 1;
     p1.jitter = 0;
     const size_t views_bytes = align256(sizeof(lp::ViewCam) * (size_t)n_views);
-    const size_t need = gen_order_bytes(&p1) + views_bytes + brick4_bytes(vol);
+    const size_t need = gen_order_bytes(&p1) + views_bytes + brick4_bytes(vol) + surface_range_bytes(&p1);
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -384,8 +438,14 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
     hipError_t e = hipMemcpyAsync(dv, vc.data(), sizeof(lp::ViewCam) * (size_t)n_views, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
-    if (e == hipSuccess) e = setup_tracking(T, vol, medium, &p1, w, s);
-    if (e == hipSuccess) e = lp::launch_generate_wave(T, vol->type, lp::kFwd, s);
+    if (p1.surface) {
+        if (e == hipSuccess)
+            e = run_surface(T, vol, medium, &p1, w,
+                            (float*)(w + gen_order_bytes(&p1) + views_bytes + brick4_bytes(vol)), s);
+    } else {
+        if (e == hipSuccess) e = setup_tracking(T, vol, medium, &p1, w, s);
+        if (e == hipSuccess) e = lp::launch_generate_wave(T, vol->type, lp::kFwd, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "lf_render_views");
     return LF_OK;
 }
@@ -435,7 +495,7 @@ int lf_majorant_grid(const lf_volume* vol, const lf_medium* sample, const lf_gen
     if (G < 1) return fail(LF_E_ARG, "majorant_grid must be >= 1 for lf_majorant_grid");
     hipError_t e = lp::launch_majorant_grid(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, G,
                                             sample->lut, sample->lut_size, sample->density_scale, vol->vmin,
-                                            vol->vmax, out, (hipStream_t)stream);
+                                            vol->vmax, out, nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lf_majorant_grid");
     return LF_OK;
 }
@@ -449,6 +509,7 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
         (r = check_params(params, true)))
         return r;
     if (!d_lf || !d_lut || !d_scale) return fail(LF_E_ARG, "d_lf, d_lut and d_scale must be non-NULL");
+    if (params->surface) return fail(LF_E_UNSUPPORTED, "the adjoint does not apply to the isosurface variant");
     // majorant, counters, spatial orders, list of rays with a nonzero adjoint,
     // then the brick copy of the volume
     const long long re = params->row_end <= 0 ? stored_rows(params) : params->row_end;

@@ -74,7 +74,7 @@ __device__ __forceinline__ int floor_div_i(int a, int b) {  // b > 0
 template <typename T>
 __global__ __launch_bounds__(1024) void majorant_grid_kernel(const T* vol, int layout, int nx, int ny, int nz, int G,
                                                              const float* lut, int lut_n, float scale, double vmin,
-                                                             double vmax, float* out) {
+                                                             double vmax, float* out, float* range) {
     __shared__ float rlo[1024], rhi[1024];
     const int cell = blockIdx.x;
     const int c[3] = {cell % G, (cell / G) % G, cell / (G * G)};
@@ -111,6 +111,11 @@ __global__ __launch_bounds__(1024) void majorant_grid_kernel(const T* vol, int l
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
+    if (range) {  // raw range of the cell's block (isosurface variant)
+        range[2 * cell] = rlo[0];
+        range[2 * cell + 1] = rhi[0];
+    }
+    if (!out) return;
     // window position of the range ends in double, as the definition states
     const double last = (double)(lut_n - 1);
     const double slo = fmin(fmax(((double)rlo[0] - vmin) / (vmax - vmin), 0.0), 1.0);
@@ -130,17 +135,17 @@ __global__ __launch_bounds__(1024) void majorant_grid_kernel(const T* vol, int l
 
 hipError_t launch_majorant_grid(const void* vol, int vtype, int layout, int nx, int ny, int nz, int G,
                                 const float* lut, int lut_n, float scale, double vmin, double vmax, float* out,
-                                hipStream_t s) {
+                                float* range, hipStream_t s) {
     const unsigned cells = (unsigned)(G * G * G);
     if (vtype == 0)
         majorant_grid_kernel<uint8_t><<<cells, 1024, 0, s>>>((const uint8_t*)vol, layout, nx, ny, nz, G, lut, lut_n,
-                                                             scale, vmin, vmax, out);
+                                                             scale, vmin, vmax, out, range);
     else if (vtype == 1)
         majorant_grid_kernel<uint16_t><<<cells, 1024, 0, s>>>((const uint16_t*)vol, layout, nx, ny, nz, G, lut,
-                                                              lut_n, scale, vmin, vmax, out);
+                                                              lut_n, scale, vmin, vmax, out, range);
     else
         majorant_grid_kernel<float><<<cells, 1024, 0, s>>>((const float*)vol, layout, nx, ny, nz, G, lut, lut_n,
-                                                           scale, vmin, vmax, out);
+                                                           scale, vmin, vmax, out, range);
     return hipGetLastError();
 }
 

@@ -55,7 +55,8 @@ hipError_t launch_wave_setup(const TraceParams& P, const float* sample_lut, int 
                              hipStream_t s);
 hipError_t launch_majorant_grid(const void* vol, int vtype, int layout, int nx, int ny, int nz, int G,
                                 const float* lut, int lut_n, float scale, double vmin, double vmax, float* out,
-                                hipStream_t s);
+                                float* range, hipStream_t s);
+hipError_t launch_surface(const TraceParams& P, int vtype, hipStream_t s);
 hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipStream_t s);
 hipError_t launch_active_rays(const TraceParams& P, hipStream_t s);
 hipError_t launch_zero(float* p, long long n, hipStream_t s);

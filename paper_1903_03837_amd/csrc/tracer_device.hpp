@@ -93,6 +93,11 @@ struct TraceParams {
     // majorant grid: grid_n^3 cell majorants (x fastest) over the volume box;
     // grid_n = 1 with maj = sigbar is the global majorant
     int32_t grid_n, nz;
+    // isosurface variant: isovalue, half the smallest voxel extent, raw
+    // [lo, hi] per grid cell
+    int32_t surface;
+    float iso, half_voxel;
+    const float* srange;
     // ground-truth views (views != nullptr): camera rays instead of the SF ray
     // set, 8 x 8 pixel tiles, stream key = (view * H + y) * W + x
     const ViewCam* views;
