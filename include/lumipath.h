@@ -193,10 +193,12 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
  *        [origin_rows][N][3]) is incremented by its transpose (atomics; lf
  *        unused).
  *   nn_out: NULL or int32 [n_views][H][W][2], nearest (i, j), -1 on a miss.
- *   cams: host array of n_views cameras, each eye outside S. */
-int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams,
-              int32_t n_views, int32_t W, int32_t H, int32_t K, int32_t mode, float* img,
-              float* d_lf, int32_t* nn_out, void* stream);
+ *   cams: host array of n_views cameras, each eye outside S.
+ *   ws / ws_bytes: workspace for the point tables of both SF sets (16 bytes
+ *   per point, filled by the call); ws == NULL only sets *ws_bytes. */
+int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
+              int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out, void* ws,
+              size_t* ws_bytes, void* stream);
 
 /* Ground-truth views: the path tracer of lf_generate along pinhole camera
  * rays, the reference the paper compares its light-field views with (Sec. 4

@@ -95,7 +95,7 @@ def library():
         L.lf_generate.argtypes = [P, P, P, P, P, C.c_int32, P, P, C.POINTER(C.c_size_t), P]
         L.lf_generate_backward.argtypes = [P, P, P, P, P, P, P, P, C.POINTER(C.c_size_t), P]
         L.lf_lookup.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                P, P, P, P]
+                                P, P, P, P, C.POINTER(C.c_size_t), P]
         L.lf_majorant_grid.argtypes = [P, P, P, P, P]
         L.lf_render_views.argtypes = [P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P,
                                       C.POINTER(C.c_size_t), P]
@@ -387,8 +387,9 @@ def lookup(lf: torch.Tensor, prm: GenParams, cams: Sequence[Camera], width: int,
     nn = torch.empty((V, height, width, 2), dtype=torch.int32, device=lf.device) if with_nn else None
     p = prm.c()
     cs = _cams(cams)
-    _check(library().lf_lookup(_ptr(lf), dt, C.byref(p), cs, V, width, height, K, 0, _ptr(img), None,
-                               _ptr(nn), _stream()))
+    args = [_ptr(lf), dt, C.byref(p), cs, V, width, height, K, 0, _ptr(img), None, _ptr(nn)]
+    ws, sz = _workspace(library().lf_lookup, *args)
+    _check(library().lf_lookup(*args, _ptr(ws), C.byref(sz), _stream()))
     return (img, nn) if with_nn else img
 
 
@@ -402,8 +403,9 @@ def lookup_adjoint(dimg: torch.Tensor, prm: GenParams, cams: Sequence[Camera], K
     _need(d_lf, prm.rows * prm.N * 3, torch.float32, "d_lf")
     p = prm.c()
     cs = _cams(cams)
-    _check(library().lf_lookup(None, 0, C.byref(p), cs, V, W, H, K, 1, _ptr(dimg), _ptr(d_lf), None,
-                               _stream()))
+    args = [None, 0, C.byref(p), cs, V, W, H, K, 1, _ptr(dimg), _ptr(d_lf), None]
+    ws, sz = _workspace(library().lf_lookup, *args)
+    _check(library().lf_lookup(*args, _ptr(ws), C.byref(sz), _stream()))
     return d_lf
 
 

@@ -543,8 +543,8 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
 }
 
 int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
-              int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out,
-              void* stream) {
+              int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out, void* ws,
+              size_t* ws_bytes, void* stream) {
     g_err.clear();
     int r;
     if ((r = check_params(params, false))) return r;
@@ -558,6 +558,15 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
     if (!img) return fail(LF_E_ARG, "img is NULL");
     if (mode == LF_LOOKUP_FORWARD && !lf) return fail(LF_E_ARG, "lf is NULL");
     if (mode == LF_LOOKUP_ADJOINT && !d_lf) return fail(LF_E_ARG, "d_lf is NULL");
+    // workspace: the point tables of both SF sets
+    const size_t tab_o_bytes = align256(16 * (size_t)params->M);
+    const size_t need = tab_o_bytes + align256(16 * (size_t)params->N);
+    int rw = check_workspace(ws, ws_bytes, need);
+    if (rw == 1) {
+        *ws_bytes = need;
+        return LF_OK;
+    }
+    if (rw) return rw;
     const double R = params->radius;
     lp::LookupParams L;
     std::memset(&L, 0, sizeof(L));
@@ -578,6 +587,8 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
     L.img = img;
     L.d_lf = d_lf;
     L.nn = nn_out;
+    L.tab_o = (const float4*)ws;
+    L.tab_d = (const float4*)((char*)ws + tab_o_bytes);
     // per-view geometry in double, rounded once to float
     std::vector<lp::ViewGeom> geo((size_t)n_views);
     for (int v = 0; v < n_views; ++v) {
@@ -621,6 +632,8 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
         g.sy = (float)th;
     }
     hipStream_t s = (hipStream_t)stream;
+    hipError_t et = lp::launch_sf_tables(L, s);
+    if (et != hipSuccess) return hip_fail(et, "lf_lookup (point tables)");
     for (int v0 = 0; v0 < n_views; v0 += lp::kMaxViewsPerLaunch) {
         const int nv = std::min(lp::kMaxViewsPerLaunch, n_views - v0);
         L.view0 = v0;

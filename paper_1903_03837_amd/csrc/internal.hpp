@@ -30,6 +30,8 @@ struct LookupParams {
     float* img;
     float* d_lf;
     int32_t* nn;
+    const float4* tab_o;    // SF point tables (workspace), float4 per point
+    const float4* tab_d;
     ViewGeom v[kMaxViewsPerLaunch];
 };
 
@@ -61,5 +63,6 @@ hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipSt
 hipError_t launch_active_rays(const TraceParams& P, hipStream_t s);
 hipError_t launch_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s);
+hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s);
 
 }  // namespace lp

@@ -111,12 +111,12 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
             float da[KMAX], db[KMAX];
             {
                 Cand9 C;
-                sf_nearest(P.M, P.invM, qo, sf_zone(P.M, qo.z), C);
+                sf_nearest(P.M, P.invM, SfTable{P.tab_o}, qo, sf_zone(P.M, qo.z), C);
                 select_k<KMAX>(C, P.K, ia, da);
             }
             {
                 Cand9 C;
-                sf_nearest(P.N, P.invN, qd, sf_zone(P.N, qd.z), C);
+                sf_nearest(P.N, P.invN, SfTable{P.tab_d}, qd, sf_zone(P.N, qd.z), C);
                 select_k<KMAX>(C, P.K, jb, db);
             }
             const float* g = P.img + 3 * pix;
@@ -201,13 +201,13 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
     {
         Cand9 C;
         const int k = sf_zone(P.M, qo.z);
-        sf_nearest(P.M, P.invM, qo, k, C);
+        sf_nearest(P.M, P.invM, SfTable{P.tab_o}, qo, k, C);
         select_k<KMAX>(C, P.K, ia, da);
     }
     {
         Cand9 C;
         const int k = sf_zone(P.N, qd.z);
-        sf_nearest(P.N, P.invN, qd, k, C);
+        sf_nearest(P.N, P.invN, SfTable{P.tab_d}, qd, k, C);
         select_k<KMAX>(C, P.K, jb, db);
     }
     if (P.nn) {
@@ -282,6 +282,20 @@ static hipError_t launch_lookup_dt(const LookupParams& P, int mode, hipStream_t 
     }
 }
 
+// Point table of an SF set (float4 per point, w unused) for the lookups.
+__global__ void sf_table_kernel(int n, float inv_n, float4* t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const f3 p = sf_point(n, i, inv_n);
+    t[i] = make_float4(p.x, p.y, p.z, 0.0f);
+}
+
+hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s) {
+    sf_table_kernel<<<(P.M + 255) / 256, 256, 0, s>>>(P.M, P.invM, (float4*)P.tab_o);
+    sf_table_kernel<<<(P.N + 255) / 256, 256, 0, s>>>(P.N, P.invN, (float4*)P.tab_d);
+    return hipGetLastError();
+}
+
 hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s) {
     if (P.K == 1) return launch_lookup_dt<1>(P, mode, s);
     if (P.K <= 5) return launch_lookup_dt<5>(P, mode, s);
@@ -308,7 +322,7 @@ __global__ void query_kernel(int n, float inv_n, float inv_r, const float* query
     const f3 v = normalize(mk3(query[3 * q], query[3 * q + 1], query[3 * q + 2]));
     Cand9 C;
     const int k = sf_zone(n, v.z);
-    sf_nearest(n, inv_n, v, k, C);
+    sf_nearest(n, inv_n, SfEval{n, inv_n}, v, k, C);
     int id[KMAX];
     float d2[KMAX];
     select_k<KMAX>(C, K, id, d2);

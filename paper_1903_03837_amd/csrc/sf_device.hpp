@@ -88,6 +88,22 @@ __device__ __forceinline__ f3 sf_point(int n, int i, float inv_n) {
     return {c * st, s * st, z};
 }
 
+// Point sources for the inverse mapping: evaluated on the fly, or read from
+// a table the same function filled (identical values, so identical
+// decisions).
+struct SfEval {
+    int n;
+    float inv_n;
+    __device__ __forceinline__ f3 operator()(int i) const { return sf_point(n, i, inv_n); }
+};
+struct SfTable {
+    const float4* t;
+    __device__ __forceinline__ f3 operator()(int i) const {
+        const float4 v = t[i];
+        return {v.x, v.y, v.z};
+    }
+};
+
 __device__ __forceinline__ int fib(int k) {
     // F(0..24); k stays below 20 for n <= 65535
     constexpr int t[25] = {0,   1,   1,   2,    3,    5,    8,    13,   21,   34,    55,    89,   144,
@@ -118,7 +134,8 @@ __device__ __forceinline__ bool closer(float da, int ia, float db, int ib) {
 }
 
 // Nearest point by the lattice-cell corners (no descent yet).
-__device__ __forceinline__ int sf_cell_nearest(int n, float inv_n, f3 q, int k, float& best_d2) {
+template <class Pts>
+__device__ __forceinline__ int sf_cell_nearest(int n, float inv_n, const Pts& pts, f3 q, int k, float& best_d2) {
     const int F0 = fib(k), F1 = fib(k + 1);
     const float b00 = sf_dphi(F0), b01 = sf_dphi(F1);
     const float b10 = -2.0f * (float)F0 * inv_n, b11 = -2.0f * (float)F1 * inv_n;
@@ -135,7 +152,7 @@ __device__ __forceinline__ int sf_cell_nearest(int n, float inv_n, f3 q, int k, 
         zc = fminf(fmaxf(zc, -1.0f), 1.0f) * 2.0f - zc;  // mirror heights past a pole
         int i = (int)floorf(0.5f * (float)n * (1.0f - zc));
         i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
-        const float d = dist2(q, sf_point(n, i, inv_n));
+        const float d = dist2(q, pts(i));
         if (closer(d, i, bd, best)) {
             bd = d;
             best = i;
@@ -152,7 +169,8 @@ struct Cand9 {
     int idx[9];
     float d2[9];
 };
-__device__ __forceinline__ void sf_candidates(int n, float inv_n, f3 q, int k, int c, Cand9& C) {
+template <class Pts>
+__device__ __forceinline__ void sf_candidates(int n, const Pts& pts, f3 q, int k, int c, Cand9& C) {
     const int f1 = fib(k - 1), f2 = fib(k), f3v = fib(k + 1), f4 = fib(k + 2);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -166,17 +184,18 @@ __device__ __forceinline__ void sf_candidates(int n, float inv_n, f3 q, int k, i
         const bool dup = (t == 1 || t == 2) && f1 == f2;
         const bool ok = ci >= 0 && ci < n && !dup;
         C.idx[t] = ok ? ci : 0x7fffff00 + t;
-        C.d2[t] = ok ? dist2(q, sf_point(n, ci, inv_n)) : 3.402823466e38f;
+        C.d2[t] = ok ? dist2(q, pts(ci)) : 3.402823466e38f;
     }
 }
 
 // Nearest point: lattice corners, then descent over the candidate set until
 // the centre is the closest candidate.  Leaves that final set in C.
-__device__ __forceinline__ int sf_nearest(int n, float inv_n, f3 q, int k, Cand9& C) {
+template <class Pts>
+__device__ __forceinline__ int sf_nearest(int n, float inv_n, const Pts& pts, f3 q, int k, Cand9& C) {
     float bd;
-    int c = sf_cell_nearest(n, inv_n, q, k, bd);
+    int c = sf_cell_nearest(n, inv_n, pts, q, k, bd);
     for (int it = 0; it < 16; ++it) {
-        sf_candidates(n, inv_n, q, k, c, C);
+        sf_candidates(n, pts, q, k, c, C);
         int best = C.idx[0];
         float bdd = C.d2[0];
 #pragma unroll

@@ -173,7 +173,9 @@ def test_points_rejects(lp):
 def lookup(lp, cams, K=5, mode=0, W=8, H=8, lf=FAKE, img=FAKE, d_lf=None):
     _, _, _, prm = scene(lp)
     arr = lp._cams(cams)
-    return lp.library().lf_lookup(lf, 0, C.byref(prm), arr, len(cams), W, H, K, mode, img, d_lf, None, None)
+    sz = C.c_size_t(1 << 20)
+    return lp.library().lf_lookup(lf, 0, C.byref(prm), arr, len(cams), W, H, K, mode, img, d_lf, None, FAKE,
+                                  C.byref(sz), None)
 
 
 def test_lookup_rejects(lp):
@@ -190,6 +192,20 @@ def test_lookup_rejects(lp):
     assert lookup(lp, [ok], lf=None) == LF_E_ARG
     assert lookup(lp, [ok], mode=1, d_lf=None) == LF_E_ARG
     assert lookup(lp, [ok], W=0) == LF_E_ARG
+
+
+def test_lookup_workspace_query(lp):
+    _, _, _, prm = scene(lp)
+    ok = lp.Camera((5, 0, 0), (0, 0, 0), (0, 0, 1), 0.5)
+    arr = lp._cams([ok])
+    sz = C.c_size_t(0)
+    r = lp.library().lf_lookup(FAKE, 0, C.byref(prm), arr, 1, 8, 8, 5, 0, FAKE, None, None, None, C.byref(sz),
+                               None)
+    assert r == LF_OK and sz.value == 2 * 1024  # the point tables of 64 + 64 SF points, 16 B each
+    sz = C.c_size_t(100)
+    r = lp.library().lf_lookup(FAKE, 0, C.byref(prm), arr, 1, 8, 8, 5, 0, FAKE, None, None, FAKE, C.byref(sz),
+                               None)
+    assert r == LF_E_WORKSPACE
 
 
 def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
