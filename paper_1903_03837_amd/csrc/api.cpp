@@ -434,8 +434,16 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
     T.vtx = (W + 7) / 8;
     T.vtiles = T.vtx * ((H + 7) / 8);
     hipStream_t s = (hipStream_t)stream;
-    // the host array is staged by the runtime before the call returns
-    hipError_t e = hipMemcpyAsync(dv, vc.data(), sizeof(lp::ViewCam) * (size_t)n_views, hipMemcpyHostToDevice, s);
+    // the views travel as kernel arguments into the workspace (stream-ordered;
+    // no host buffer has to outlive the call)
+    hipError_t e = hipSuccess;
+    for (int v0 = 0; v0 < n_views && e == hipSuccess; v0 += lp::kViewBatch) {
+        lp::ViewBatch vb;
+        vb.first = v0;
+        vb.count = std::min(lp::kViewBatch, n_views - v0);
+        for (int v = 0; v < vb.count; ++v) vb.v[v] = vc[v0 + v];
+        e = lp::launch_fill_views(vb, dv, s);
+    }
     if (e == hipSuccess)
         e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
     if (p1.surface) {

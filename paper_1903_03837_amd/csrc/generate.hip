@@ -149,4 +149,13 @@ hipError_t launch_majorant_grid(const void* vol, int vtype, int layout, int nx, 
     return hipGetLastError();
 }
 
+__global__ void fill_views_kernel(ViewBatch b, ViewCam* dst) {
+    if ((int)threadIdx.x < b.count) dst[b.first + threadIdx.x] = b.v[threadIdx.x];
+}
+
+hipError_t launch_fill_views(const ViewBatch& b, ViewCam* dst, hipStream_t s) {
+    fill_views_kernel<<<1, kViewBatch, 0, s>>>(b, dst);
+    return hipGetLastError();
+}
+
 }  // namespace lp

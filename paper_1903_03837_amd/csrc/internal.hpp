@@ -59,6 +59,14 @@ hipError_t launch_majorant_grid(const void* vol, int vtype, int layout, int nx, 
                                 const float* lut, int lut_n, float scale, double vmin, double vmax, float* out,
                                 float* range, hipStream_t s);
 hipError_t launch_surface(const TraceParams& P, int vtype, hipStream_t s);
+
+// Up to kViewBatch ground-truth views per argument block.
+constexpr int kViewBatch = 32;
+struct ViewBatch {
+    ViewCam v[kViewBatch];
+    int32_t first, count;
+};
+hipError_t launch_fill_views(const ViewBatch& b, ViewCam* dst, hipStream_t s);
 hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipStream_t s);
 hipError_t launch_active_rays(const TraceParams& P, hipStream_t s);
 hipError_t launch_zero(float* p, long long n, hipStream_t s);
