@@ -5,7 +5,7 @@ One step = one pass of the whole path over the CT-like workload (256^3 u16
 phantom, M = N = 2048 spherical-Fibonacci points, 4.19M rays, 64 samples per
 ray, 8 bounces, HG g = 0.3, area light):
   lf_points (SF table) -> lf_generate (FP32 light field, 5^3 majorant grid) -> lf_lookup (32 views
-  of 1920 x 1080, K = 5) -> L2 view loss gradient -> lf_lookup adjoint ->
+  of 1920 x 1080, K = 5) -> gradient of 1/2 |views - targets|^2 -> lf_lookup adjoint ->
   lf_generate_backward (d LUT, d density scale).
 `value` = M*N*spp path samples per second of the whole step.  One JSON line
 on stdout; progress on stderr.  Inputs are seeded synthetic data (lfsynth).
@@ -84,6 +84,166 @@ def cpu_baseline(scene, seconds, nrays_probe=20000):
                       f"({dt:.1f} s, FP64 C, pthreads)"}, ks, ref
 
 
+def sweep_configs(configs, with_oracle=True, calib_copy_mb=0):
+    """Generation on each workload c1..c5 at full size: throughput, work
+    counts, error against the FP64 oracle on seeded ray samples, FP16/BF16
+    storage error (c4), adjoint checks and timing (c5).  One JSON line per
+    workload on stdout.  Without the oracle (counter runs) the error and
+    oracle fields are left out."""
+    import numpy as np
+    import torch
+
+    import lfsynth as S
+    import paper_1903_03837_amd as lp
+
+    dev = "cuda"
+    if with_oracle:
+        # the CPU baseline and error reference of each workload
+        from oracle import oracle as orc
+        threads = orc.default_threads()
+    sample_rays = {1: None, 2: 20000, 3: 50000, 4: None, 5: 20000}
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def rel_errors(got, ref):
+        # aggregate L1 ratio, then per-value relative errors (values below
+        # 1e-3 of the mean radiance are measured against that floor)
+        den = np.abs(ref).sum()
+        floor = 1e-3 * np.abs(ref).mean()
+        rel = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
+        return {"rel_l1": float(np.abs(got - ref).sum() / den), "mean_rel": float(rel.mean()),
+                "median_rel": float(np.median(rel)), "p99_rel": float(np.quantile(rel, 0.99)),
+                "max_rel": float(rel.max()), "frac_within_1e-3": float((rel <= 1e-3).mean())}
+
+    def storage_rounding(low, f32, tiny):
+        # relative change made by storing the same FP32 values in a narrower
+        # type, over values in that type's normal range
+        m = np.abs(f32) >= tiny
+        return {"rel_l1": float(np.abs(low - f32).sum() / np.abs(f32).sum()),
+                "max_rel_normal": float((np.abs(low - f32)[m] / np.abs(f32)[m]).max())}
+
+    for c in configs:
+        log(f"configs: workload c{c}")
+        sc = S.config(c)
+        vol, med, light, prm, cams = lp.device_scene(sc)
+        M, N, spp = prm.M, prm.N, prm.spp
+        stats = torch.zeros(5, dtype=torch.int64, device=dev)
+        lf = lp.generate(vol, med, light, prm, stats=stats)
+        torch.cuda.synchronize()
+        tent, shadow, real, samples, cells = (int(x) for x in stats.cpu().numpy())
+        reps = 2 if M * N > 10_000_000 else 5
+        ms = timed(lambda: lp.generate(vol, med, light, prm, out=lf), reps)
+        log(f"configs: c{c} generation {ms:.2f} ms")
+        rays = M * N - (M if M == N else 0)
+        row = {"workload": sc.name, "M": M, "N": N, "spp": spp, "grid": prm.grid, "rays": rays,
+               "generate_ms": ms, "samples_per_s": M * N * spp / (ms / 1e3),
+               "tentative_collisions_per_s": tent / (ms / 1e3), "collisions_per_sample": tent / samples,
+               "cell_steps_per_sample": cells / samples,
+               "gather_GBps": (tent + shadow) * 8 * np.dtype(sc.volume.data.dtype).itemsize / (ms / 1e3) / 1e9,
+               "real_collisions_per_sample": real / samples, "field_bytes_f32": lf.numel() * 4}
+        if c == 1:
+            ks = np.arange(M * N)
+            ks = ks[(ks // N) != (ks % N)]
+        elif sample_rays[c] is None:
+            ks = S.random_rays(M, N, (M * N) // 100, 9000 + c)
+        else:
+            ks = S.random_rays(M, N, sample_rays[c], 9000 + c)
+        idx = torch.from_numpy(ks).to(dev)
+        got = lf.reshape(-1, 3)[idx].double().cpu().numpy()
+        ref = None
+        if with_oracle:
+            t0 = time.perf_counter()
+            ref = orc.generate(sc, ks, nthreads=threads)
+            t_orc = time.perf_counter() - t0
+            log(f"configs: c{c} oracle on {len(ks)} rays {t_orc:.1f} s")
+            row["f32_vs_oracle"] = dict(rays=int(len(ks)), **rel_errors(got, ref))
+            row["oracle_samples_per_s"] = len(ks) * spp / t_orc
+            row["oracle_cores"] = threads
+        if c == 4:
+            for name in ("f16", "bf16"):
+                low = lp.generate(vol, med, light, prm, dtype=name)
+                torch.cuda.synchronize()
+                ms_low = timed(lambda: lp.generate(vol, med, light, prm, dtype=name, out=low), reps)
+                log(f"configs: c{c} {name} generation {ms_low:.2f} ms")
+                g = low.reshape(-1, 3)[idx].double().cpu().numpy()
+                if ref is not None:
+                    row[f"{name}_vs_oracle"] = rel_errors(g, ref)
+                row[f"{name}_generate_ms"] = ms_low
+                row[f"{name}_field_bytes"] = low.numel() * low.element_size()
+                row[f"{name}_vs_f32"] = storage_rounding(g, got, 6.1e-5 if name == "f16" else 1.2e-38)
+                del low
+                torch.cuda.empty_cache()
+        if c == 5:
+            # adjoint of 1/2 |views - targets|^2 over 16 views of 512^2, and its checks
+            W, H = sc.width, sc.height
+            tm = S.target_medium(sc)
+            tmed = lp.Medium(torch.from_numpy(tm.lut).to(dev), tm.scale)
+            target = lp.lookup(lp.generate(vol, tmed, light, prm), prm, cams, W, H, sc.K)
+            img = lp.lookup(lf, prm, cams, W, H, sc.K)
+            d_lf = lp.lookup_adjoint(img - target, prm, cams, sc.K)
+            ms_bwd = timed(lambda: lp.generate_backward(vol, med, light, prm, d_lf), 5)
+            log(f"configs: c{c} adjoint {ms_bwd:.2f} ms")
+            d_lut, d_scale = lp.generate_backward(vol, med, light, prm, d_lf)
+            torch.cuda.synchronize()
+            g = np.concatenate([d_lut.cpu().numpy().reshape(-1), d_scale.cpu().numpy()]).astype(np.float64)
+            adj = d_lf.double()
+            lut0 = sc.medium.lut
+
+            def loss(lut, scale):
+                m = lp.Medium(torch.from_numpy(lut).to(dev), scale)
+                L = lp.generate(vol, m, light, prm, sample=med)
+                return float((L.double() * adj).sum())
+
+            # central differences in frozen sampling on the 24 largest LUT
+            # coordinates of the gradient and the density scale
+            order = np.argsort(-np.abs(g[:-1]))[:24]
+            h = 1e-3
+            fd, gv = [], []
+            for e in order:
+                a, b = divmod(int(e), 4)
+                lp_, lm = lut0.copy(), lut0.copy()
+                lp_[a, b] += h
+                lm[a, b] -= h
+                fd.append((loss(lp_, sc.medium.scale) - loss(lm, sc.medium.scale)) / (float(lp_[a, b]) - float(lm[a, b])))
+                gv.append(g[e])
+            fd.append((loss(lut0, sc.medium.scale + h) - loss(lut0, sc.medium.scale - h)) / (2 * h))
+            gv.append(g[-1])
+            fd, gv = np.array(fd), np.array(gv)
+            row["adjoint"] = {"views": len(cams), "width": W, "height": H, "backward_ms": ms_bwd,
+                              "adjoint_forward_ratio": ms_bwd / ms,
+                              "vs_central_differences_h1e-3": float(np.linalg.norm(gv - fd) / np.linalg.norm(fd)),
+                              "fd_coordinates": len(fd)}
+            if with_oracle:
+                # the oracle gradient of the same adjoint restricted to a ray subset
+                sub = S.random_rays(M, N, 20000, 9105)
+                adj_sub = torch.zeros_like(d_lf)
+                sidx = torch.from_numpy(sub).to(dev)
+                adj_sub.view(-1, 3)[sidx] = d_lf.view(-1, 3)[sidx]
+                gs_lut, gs_scale = lp.generate_backward(vol, med, light, prm, adj_sub)
+                o_lut, o_scale = orc.gradient(sc, sub, adj_sub.view(-1, 3)[sidx].double().cpu().numpy())
+                gs = np.concatenate([gs_lut.cpu().numpy().reshape(-1), [float(gs_scale)]]).astype(np.float64)
+                os_ = np.concatenate([o_lut.reshape(-1), [o_scale]])
+                row["adjoint"]["vs_oracle_gradient_20000_rays"] = float(np.linalg.norm(gs - os_) / np.linalg.norm(os_))
+        print(json.dumps(row), flush=True)
+        del lf
+        torch.cuda.empty_cache()
+    if calib_copy_mb:
+        n = calib_copy_mb * (1 << 20) // 4
+        a_ = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        b_ = torch.empty_like(a_)
+        b_.copy_(a_)
+        torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,11 +253,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--configs", type=str, default="",
+                    help="instead of the step, measure generation on these workloads (e.g. 1,2,3,4,5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the light field shards by rows "
               "of origins; see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.configs:
+        sweep_configs([int(c) for c in args.configs.split(",")], with_oracle=not args.no_cpu_baseline,
+                      calib_copy_mb=args.calib_copy_mb)
+        return
 
     import numpy as np
     import torch
@@ -115,6 +281,7 @@ def main():
     dev = "cuda"
     lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
     img = torch.empty((V, H, W, 3), dtype=torch.float32, device=dev)
+    dimg = torch.empty_like(img)
     d_lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
 
     # seeded target views: the same scene under the perturbed medium
@@ -142,7 +309,8 @@ def main():
         evs[2].record(stream)
         lp.lookup(lf, prm, cams, W, H, K, img=img)
         evs[3].record(stream)
-        dimg = 2.0 * (img - target)
+        # loss = 1/2 |img - target|^2 over all pixels: its gradient in one pass
+        torch.sub(img, target, out=dimg)
         evs[4].record(stream)
         d_lf.zero_()
         lp.lookup_adjoint(dimg, prm, cams, K, d_lf=d_lf)
@@ -229,7 +397,7 @@ def main():
         "config": {
             "workload": "CT-like phantom 256^3 u16 (12 nested ellipsoids), M=N=2048 SF points (4.19M rays), "
                         "64 spp, 8 bounces, HG g=0.3, area light, 5^3 majorant grid, FP32 light field; lookup of "
-                        "32 views 1920x1080 K=5; adjoint of an L2 view loss",
+                        "32 views 1920x1080 K=5; adjoint of the loss 1/2 |views - targets|^2",
             "M": M, "N": N, "spp": spp, "max_bounces": prm.max_bounces, "views": V, "width": W, "height": H,
             "K": K, "volume": "256^3 u16 linear", "majorant_grid": prm.grid,
         },

@@ -257,6 +257,18 @@ __device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, float& tn
     return t0 < t1;
 }
 
+// True when the light-field ray from SF origin po (unit sphere) along d0
+// misses the volume box in every sample.  The jitter moves the origin by less
+// than jit_rad, so the test clips against the box grown by jit_rad plus a
+// margin far above FP32 rounding; without jitter it is the sample's own clip
+// (the same function on the same origin).
+__device__ __forceinline__ bool misses_box(const TraceParams& P, f3 O, f3 bmin, f3 bmax, f3 po, f3 d0) {
+    const float pad = P.jitter ? P.jit_rad * 1.001f + 1e-5f * P.R : 0.0f;
+    float tn, tf;
+    return !clip_box(mk3(bmin.x - pad, bmin.y - pad, bmin.z - pad), mk3(bmax.x + pad, bmax.y + pad, bmax.z + pad),
+                     O + po * P.R, d0, tn, tf);
+}
+
 // Orthonormal completion of unit n (Duff et al. 2017).
 __device__ __forceinline__ void frame(f3 n, f3& t1, f3& t2) {
     const float sg = n.z >= 0.0f ? 1.0f : -1.0f;

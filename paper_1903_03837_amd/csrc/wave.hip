@@ -41,7 +41,9 @@
 
 namespace lp {
 
-template <int VT, int MODE>
+// STATS: the work counters of `stats` are kept (a separate instantiation, so
+// the plain kernel spends no registers on them).
+template <int VT, int MODE, bool STATS>
 __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     extern __shared__ float4 smem[];
     float4* lut_e = smem;
@@ -179,6 +181,17 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         b = 0;
                         blk = 0;
                         mode = kStart;
+                        // A ray that misses the volume box in every sample: all
+                        // samples but the last are added here (each is the
+                        // environment radiance), and the last one runs as usual.
+                        // (The adjoint's ray list leaves such rays out.)
+                        if constexpr (MODE != kGrad) {
+                            if (misses_box(P, O, bmin, bmax, po, d0)) {
+                                for (int s2 = 1; s2 < P.spp; ++s2) acc = acc + env;
+                                cnt.samples += (uint32_t)(P.spp - 1);
+                                s = P.spp - 1;
+                            }
+                        }
                     }
                 }
             }
@@ -442,7 +455,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
         return;
     }
 
-    if (P.stats) {
+    if (STATS) {
         const uint32_t a = wave_sum(cnt.tent), c = wave_sum(cnt.shadow), e = wave_sum(cnt.real),
                        f = wave_sum(cnt.samples);
         const unsigned long long cs = wave_sum64(cnt.cells);
@@ -472,7 +485,9 @@ __global__ void sf_order_kernel(int base, int count, int band, int32_t* out) {
     out[lo + rank] = base + e;
 }
 
-// Compacts the rays (in the spatial tile order) whose adjoint is nonzero.
+// Compacts the rays (in the spatial tile order) whose adjoint is nonzero and
+// which can reach the volume box (a ray that misses it in every sample has no
+// collision and so no score).
 __global__ void active_rays_kernel(TraceParams P) {
     const int rows = P.row_end - P.row_begin;
     const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
@@ -493,6 +508,12 @@ __global__ void active_rays_kernel(TraceParams P) {
                 k = (uint32_t)i * (uint32_t)P.N + (uint32_t)j;
                 const float* a = P.d_lf + 3 * (uint64_t)k;
                 take = !(P.M == P.N && i == j) && (a[0] != 0.0f || a[1] != 0.0f || a[2] != 0.0f);
+                if (take) {
+                    const f3 po = sf_point(P.M, i, 1.0f / (float)P.M);
+                    const f3 d0 = normalize(sf_point(P.N, j, 1.0f / (float)P.N) - po);
+                    take = !misses_box(P, mk3(P.O[0], P.O[1], P.O[2]), mk3(P.bmin[0], P.bmin[1], P.bmin[2]),
+                                       mk3(P.bmax[0], P.bmax[1], P.bmax[2]), po, d0);
+                }
             }
         }
         const uint64_t m = __ballot(take);
@@ -544,7 +565,7 @@ hipError_t launch_active_rays(const TraceParams& P, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int VT, int MODE>
+template <int VT, int MODE, bool STATS>
 static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
     const long long ntiles = P.views ? (long long)P.nviews * P.vtiles : ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
@@ -556,21 +577,23 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE>, 256, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE, STATS>, 256, lds);
     if (e != hipSuccess) return e;
     long long blocks = (long long)cus * (per_cu > 0 ? per_cu : 1);
     // at least one tile per wave (list lengths are only known on the device;
     // waves that find no chunk exit at once)
     const long long need = (ntiles + 3) / 4;
     if (blocks > need) blocks = need;
-    gen_wave_kernel<VT, MODE><<<(unsigned)blocks, 256, lds, s>>>(P);
+    gen_wave_kernel<VT, MODE, STATS><<<(unsigned)blocks, 256, lds, s>>>(P);
     return hipGetLastError();
 }
 
 template <int VT>
 static hipError_t launch_wave_mode(const TraceParams& P, int mode, hipStream_t s) {
-    if (mode == kGrad) return launch_wave_t<VT, kGrad>(P, s);
-    return mode == kFrozen ? launch_wave_t<VT, kFrozen>(P, s) : launch_wave_t<VT, kFwd>(P, s);
+    if (mode == kGrad) return launch_wave_t<VT, kGrad, false>(P, s);
+    if (P.stats)
+        return mode == kFrozen ? launch_wave_t<VT, kFrozen, true>(P, s) : launch_wave_t<VT, kFwd, true>(P, s);
+    return mode == kFrozen ? launch_wave_t<VT, kFrozen, false>(P, s) : launch_wave_t<VT, kFwd, false>(P, s);
 }
 
 hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipStream_t s) {
