@@ -57,7 +57,10 @@ enum { LF_LOOKUP_FORWARD = 0, LF_LOOKUP_ADJOINT = 1 };
  * trilinearly (edge-clamped) and mapped through the window [vmin, vmax] onto
  * the transfer function.  brick = 0: x-fastest linear array; brick = 8: 8^3
  * bricks, bricks ordered x-fastest, voxels x-fastest inside a brick (each of
- * nx, ny, nz divisible by 8).  nx, ny, nz >= 2. */
+ * nx, ny, nz divisible by 8).  nx, ny, nz >= 2.  The tracing entry points
+ * copy the volume into their workspace as 4^3-voxel bricks placed every 3
+ * voxels (64 * prod((n - 2) / 3 + 1) voxels); a volume whose copy would exceed
+ * 2^32 voxels, or with a dimension above 65535, is rejected with LF_E_RANGE. */
 typedef struct {
     const void* data;       /* device [nx*ny*nz] of the voxel type, aligned to it */
     int32_t type;           /* LF_VOX_* */

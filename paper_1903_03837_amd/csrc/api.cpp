@@ -34,10 +34,14 @@ bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1])
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Bytes of the volume's 4^3-brick copy (dimensions padded to multiples of 4).
-size_t brick4_bytes(const lf_volume* v) {
+// Voxels of the volume's halo-brick copy (4^3-voxel bricks every 3 voxels).
+size_t brick_voxels(const lf_volume* v) {
+    return 64 * (size_t)lp::halo_bricks(v->nx) * (size_t)lp::halo_bricks(v->ny) * (size_t)lp::halo_bricks(v->nz);
+}
+
+size_t brick_copy_bytes(const lf_volume* v) {
     const size_t esz = v->type == LF_VOX_U8 ? 1 : (v->type == LF_VOX_U16 ? 2 : 4);
-    return align256(esz * 64 * (size_t)((v->nx + 3) / 4) * (size_t)((v->ny + 3) / 4) * (size_t)((v->nz + 3) / 4));
+    return align256(esz * brick_voxels(v));
 }
 
 // lf_generate workspace: majorant (offset 0), 8 tile counters (offset 64),
@@ -90,6 +94,9 @@ int check_volume(const lf_volume* v) {
     if (!v->data) return fail(LF_E_ARG, "volume data is NULL");
     if (v->type < LF_VOX_U8 || v->type > LF_VOX_F32) return fail(LF_E_ARG, "unknown voxel type %d", v->type);
     if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(LF_E_ARG, "volume dimensions must be >= 2");
+    if (v->nx > 65535 || v->ny > 65535 || v->nz > 65535 || brick_voxels(v) > 0xFFFFFFFFull)
+        return fail(LF_E_RANGE, "volume too large: its halo-brick copy (%zu voxels) needs 32-bit voxel indices",
+                    brick_voxels(v));
     if (64ull * ((v->nx + 3) / 4) * ((v->ny + 3) / 4) * ((v->nz + 3) / 4) >= (1ull << 32))
         return fail(LF_E_RANGE, "volume too large");
     const uintptr_t esz = v->type == LF_VOX_U8 ? 1 : (v->type == LF_VOX_U16 ? 2 : 4);
@@ -137,11 +144,11 @@ int check_light(const lf_light* l) {
 void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, const lf_medium* s,
                 const lf_light* l, const lf_gen_params* p) {
     std::memset(&T, 0, sizeof(T));
-    T.vol = v->data;  // replaced by the workspace's 4^3-brick copy
+    T.vol = v->data;  // replaced by the workspace's halo-brick copy
     T.nx = v->nx;
     T.ny = v->ny;
-    T.brick_row = 64 * ((v->nx + 3) / 4);
-    T.brick_slab = 64 * ((v->nx + 3) / 4) * ((v->ny + 3) / 4);
+    T.brick_row = 64 * lp::halo_bricks(v->nx);
+    T.brick_slab = 64 * lp::halo_bricks(v->nx) * lp::halo_bricks(v->ny);
     const int n[3] = {v->nx, v->ny, v->nz};
     for (int a = 0; a < 3; ++a) {
         const double ext = (double)v->box_max[a] - (double)v->box_min[a];
@@ -322,7 +329,7 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     if (!lf_out) return fail(LF_E_ARG, "lf_out is NULL");
     if (params->surface && sample && sample != eval)
         return fail(LF_E_UNSUPPORTED, "frozen sampling does not apply to the isosurface variant");
-    const size_t need = gen_order_bytes(params) + brick4_bytes(vol) + surface_range_bytes(params);
+    const size_t need = gen_order_bytes(params) + brick_copy_bytes(vol) + surface_range_bytes(params);
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -337,10 +344,10 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     T.vol = w + gen_order_bytes(params);
     const lf_medium* sm = sample ? sample : eval;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
+    hipError_t e = lp::launch_halo_bricks(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
     if (params->surface) {
         if (e == hipSuccess)
-            e = run_surface(T, vol, eval, params, w, (float*)(w + gen_order_bytes(params) + brick4_bytes(vol)), s);
+            e = run_surface(T, vol, eval, params, w, (float*)(w + gen_order_bytes(params) + brick_copy_bytes(vol)), s);
         if (e != hipSuccess) return hip_fail(e, "lf_generate (isosurface)");
         return LF_OK;
     }
@@ -413,7 +420,7 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
     p1.row_end = 1;
     p1.jitter = 0;
     const size_t views_bytes = align256(sizeof(lp::ViewCam) * (size_t)n_views);
-    const size_t need = gen_order_bytes(&p1) + views_bytes + brick4_bytes(vol) + surface_range_bytes(&p1);
+    const size_t need = gen_order_bytes(&p1) + views_bytes + brick_copy_bytes(vol) + surface_range_bytes(&p1);
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -445,11 +452,11 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
         e = lp::launch_fill_views(vb, dv, s);
     }
     if (e == hipSuccess)
-        e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
+        e = lp::launch_halo_bricks(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
     if (p1.surface) {
         if (e == hipSuccess)
             e = run_surface(T, vol, medium, &p1, w,
-                            (float*)(w + gen_order_bytes(&p1) + views_bytes + brick4_bytes(vol)), s);
+                            (float*)(w + gen_order_bytes(&p1) + views_bytes + brick_copy_bytes(vol)), s);
     } else {
         if (e == hipSuccess) e = setup_tracking(T, vol, medium, &p1, w, s);
         if (e == hipSuccess) e = lp::launch_generate_wave(T, vol->type, lp::kFwd, s);
@@ -522,7 +529,7 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     // then the brick copy of the volume
     const long long re = params->row_end <= 0 ? stored_rows(params) : params->row_end;
     const size_t list_bytes = align256(4 * (size_t)(re - params->row_begin) * (size_t)params->N);
-    const size_t need = gen_order_bytes(params) + list_bytes + brick4_bytes(vol);
+    const size_t need = gen_order_bytes(params) + list_bytes + brick_copy_bytes(vol);
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -540,7 +547,7 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     T.ray_list = (uint32_t*)(w + gen_order_bytes(params));
     T.vol = w + gen_order_bytes(params) + list_bytes;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = lp::launch_brick4(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
+    hipError_t e = lp::launch_halo_bricks(vol->data, vol->type, vol->brick, vol->nx, vol->ny, vol->nz, (void*)T.vol, s);
     if (e == hipSuccess) e = lp::launch_zero(d_lut, 4ll * medium->lut_size, s);
     if (e == hipSuccess) e = lp::launch_zero(d_scale, 1, s);
     if (e == hipSuccess) e = setup_tracking(T, vol, medium, params, w, s);

@@ -1,5 +1,5 @@
 // generate.hip -- small set-up kernels of light-field generation: zero fill,
-// the copy of the volume into 4^3 bricks, and the cell majorants of the
+// the halo-brick copy of the volume, and the cell majorants of the
 // majorant grid.
 #include <hip/hip_fp16.h>
 
@@ -18,44 +18,44 @@ hipError_t launch_zero(float* p, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Copy of the input volume (x-fastest, or 8^3 bricks) into 4^3 bricks; the
-// padding beyond nx, ny, nz is never read (fetch coordinates are clamped).
+// Halo-brick copy of the input volume (x-fastest, or 8^3 bricks): brick
+// (bx, by, bz) holds the 4^3 voxels from (3 bx, 3 by, 3 bz), so neighbouring
+// bricks share a layer and every trilinear footprint lies in one brick.
+// Voxels past the last index repeat the edge (no valid footprint reads them).
 template <typename T>
-__global__ void brick4_kernel(const T* src, int layout, int nx, int ny, int nz, int nbx, int nby, long long total,
-                              T* dst) {
+__global__ void halo_brick_kernel(const T* src, int layout, int nx, int ny, int nz, int nbx, int nby, long long total,
+                                  T* dst) {
     const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= total) return;
     const long long bk = d >> 6;
     const int w = (int)(d & 63);
     const int bx = (int)(bk % nbx), by = (int)((bk / nbx) % nby), bz = (int)(bk / ((long long)nbx * nby));
-    const int x = bx * 4 + (w & 3), y = by * 4 + ((w >> 2) & 3), z = bz * 4 + (w >> 4);
-    T v = T(0);
-    if (x < nx && y < ny && z < nz) {
-        long long si;
-        if (layout == 8) {
-            const long long b8 = (x >> 3) + (long long)(nx >> 3) * ((y >> 3) + (long long)(ny >> 3) * (z >> 3));
-            si = b8 * 512 + (x & 7) + 8 * ((y & 7) + 8 * (z & 7));
-        } else {
-            si = x + (long long)nx * (y + (long long)ny * z);
-        }
-        v = src[si];
+    const int x = min(bx * 3 + (w & 3), nx - 1), y = min(by * 3 + ((w >> 2) & 3), ny - 1),
+              z = min(bz * 3 + (w >> 4), nz - 1);
+    long long si;
+    if (layout == 8) {
+        const long long b8 = (x >> 3) + (long long)(nx >> 3) * ((y >> 3) + (long long)(ny >> 3) * (z >> 3));
+        si = b8 * 512 + (x & 7) + 8 * ((y & 7) + 8 * (z & 7));
+    } else {
+        si = x + (long long)nx * (y + (long long)ny * z);
     }
-    dst[d] = v;
+    dst[d] = src[si];
 }
 
-hipError_t launch_brick4(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst, hipStream_t s) {
-    const int nbx = (nx + 3) / 4, nby = (ny + 3) / 4, nbz = (nz + 3) / 4;
+hipError_t launch_halo_bricks(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst,
+                              hipStream_t s) {
+    const int nbx = halo_bricks(nx), nby = halo_bricks(ny), nbz = halo_bricks(nz);
     const long long total = 64ll * nbx * nby * nbz;
     const unsigned blocks = (unsigned)((total + 255) / 256);
     if (vtype == 0)
-        brick4_kernel<uint8_t><<<blocks, 256, 0, s>>>((const uint8_t*)src, layout, nx, ny, nz, nbx, nby, total,
-                                                       (uint8_t*)dst);
+        halo_brick_kernel<uint8_t><<<blocks, 256, 0, s>>>((const uint8_t*)src, layout, nx, ny, nz, nbx, nby, total,
+                                                           (uint8_t*)dst);
     else if (vtype == 1)
-        brick4_kernel<uint16_t><<<blocks, 256, 0, s>>>((const uint16_t*)src, layout, nx, ny, nz, nbx, nby, total,
-                                                        (uint16_t*)dst);
+        halo_brick_kernel<uint16_t><<<blocks, 256, 0, s>>>((const uint16_t*)src, layout, nx, ny, nz, nbx, nby,
+                                                            total, (uint16_t*)dst);
     else
-        brick4_kernel<float><<<blocks, 256, 0, s>>>((const float*)src, layout, nx, ny, nz, nbx, nby, total,
-                                                     (float*)dst);
+        halo_brick_kernel<float><<<blocks, 256, 0, s>>>((const float*)src, layout, nx, ny, nz, nbx, nby, total,
+                                                         (float*)dst);
     return hipGetLastError();
 }
 

@@ -51,7 +51,10 @@ size_t ssim_partial_count(int n_images, int W, int H);
 
 hipError_t launch_points(int n, float* xyz, const float* query, long long nq, int K, int* idx, float* w,
                          hipStream_t s);
-hipError_t launch_brick4(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst, hipStream_t s);
+// Halo bricks along an axis of n >= 2 voxels: base voxels 0 .. n-2, three per brick.
+inline int halo_bricks(int n) { return (n - 2) / 3 + 1; }
+hipError_t launch_halo_bricks(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst,
+                              hipStream_t s);
 hipError_t launch_wave_setup(const TraceParams& P, const float* sample_lut, int lut_n, float sample_scale,
                              float given, float* sigbar, unsigned int* ctr, int32_t* perm_o, int32_t* perm_d,
                              hipStream_t s);

@@ -47,8 +47,8 @@ struct ViewCam {
 };
 
 struct TraceParams {
-    // volume: the library's 4^3-brick copy (bricks x-fastest, voxels
-    // x-fastest inside a brick; 4 x 4 x 4 u16 voxels fill one 128-byte line)
+    // volume: the library's halo-brick copy (4^3-voxel bricks every 3
+    // voxels, bricks x-fastest, voxels x-fastest inside a brick)
     const void* vol;
     int32_t nx, ny;
     int32_t brick_row, brick_slab;   // 64 * bricks per row, 64 * bricks per slab
@@ -173,8 +173,12 @@ __device__ __forceinline__ float vox(const void* v, uint32_t idx) {
 }
 
 // Trilinear raw value at world point y (edge-clamped grid coordinates) from
-// the 4^3-brick copy: the 2 x 2 x 2 footprint lies in one 128-byte line for
-// (3/4)^3 of the points and in 1.95 lines on average (x-fastest rows: 4).
+// the library's halo-brick copy of the volume: bricks of 4^3 voxels placed
+// every 3 voxels, so that neighbouring bricks share one layer.  The 2 x 2 x 2
+// footprint of base voxel (ix, iy, iz) then lies whole in brick
+// (ix/3, iy/3, iz/3) at local offset (ix%3, iy%3, iz%3): one 128-byte line
+// for u16, half a line for u8, and one of two lines for f32 (or both, in one
+// case of three).  Its eight voxels sit at fixed offsets from the first.
 template <int VT>
 __device__ __forceinline__ float sample_volume(const TraceParams& P, f3 y) {
     const float gx = fminf(fmaxf(fmaf(y.x, P.ga[0], P.gb[0]), 0.0f), P.gmax[0]);
@@ -184,16 +188,15 @@ __device__ __forceinline__ float sample_volume(const TraceParams& P, f3 y) {
     const int iy = min((int)gy, P.imax[1]);
     const int iz = min((int)gz, P.imax[2]);
     const float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
-    const uint32_t x0 = (uint32_t)((ix >> 2) * 64 + (ix & 3));
-    const uint32_t x1 = (uint32_t)(((ix + 1) >> 2) * 64 + ((ix + 1) & 3));
-    const uint32_t y0 = (uint32_t)((iy >> 2) * P.brick_row + (iy & 3) * 4);
-    const uint32_t y1 = (uint32_t)(((iy + 1) >> 2) * P.brick_row + ((iy + 1) & 3) * 4);
-    const uint32_t z0 = (uint32_t)((iz >> 2) * P.brick_slab + (iz & 3) * 16);
-    const uint32_t z1 = (uint32_t)(((iz + 1) >> 2) * P.brick_slab + ((iz + 1) & 3) * 16);
-    const float v000 = vox<VT>(P.vol, x0 + y0 + z0), v100 = vox<VT>(P.vol, x1 + y0 + z0);
-    const float v010 = vox<VT>(P.vol, x0 + y1 + z0), v110 = vox<VT>(P.vol, x1 + y1 + z0);
-    const float v001 = vox<VT>(P.vol, x0 + y0 + z1), v101 = vox<VT>(P.vol, x1 + y0 + z1);
-    const float v011 = vox<VT>(P.vol, x0 + y1 + z1), v111 = vox<VT>(P.vol, x1 + y1 + z1);
+    // i / 3 as (i * 43691) >> 17, exact for i < 2^17 (dimensions are < 2^16)
+    const uint32_t bx = ((uint32_t)ix * 43691u) >> 17, by = ((uint32_t)iy * 43691u) >> 17,
+                   bz = ((uint32_t)iz * 43691u) >> 17;
+    const uint32_t lx = (uint32_t)ix - 3u * bx, ly = (uint32_t)iy - 3u * by, lz = (uint32_t)iz - 3u * bz;
+    const uint32_t base = bz * (uint32_t)P.brick_slab + by * (uint32_t)P.brick_row + bx * 64u + lz * 16u + ly * 4u + lx;
+    const float v000 = vox<VT>(P.vol, base), v100 = vox<VT>(P.vol, base + 1);
+    const float v010 = vox<VT>(P.vol, base + 4), v110 = vox<VT>(P.vol, base + 5);
+    const float v001 = vox<VT>(P.vol, base + 16), v101 = vox<VT>(P.vol, base + 17);
+    const float v011 = vox<VT>(P.vol, base + 20), v111 = vox<VT>(P.vol, base + 21);
     const float c00 = fmaf(fx, v100 - v000, v000), c10 = fmaf(fx, v110 - v010, v010);
     const float c01 = fmaf(fx, v101 - v001, v001), c11 = fmaf(fx, v111 - v011, v011);
     const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);

@@ -84,8 +84,9 @@ def test_workspace_size_query(lp):
     vol, med, light, prm = scene(lp)
     r, sz = call_generate(lp, vol, med, light, prm)
     # majorant + counters, the spatial orders of 64 origins and 64 directions,
-    # then the 4^3-brick copy of the 16^3 u8 volume
-    assert r == LF_OK and sz == 256 + 256 + 256 + 4096
+    # then the halo-brick copy of the 16^3 u8 volume: 5^3 bricks of 64 voxels
+    # (8000 B, rounded up to 256 B)
+    assert r == LF_OK and sz == 256 + 256 + 256 + 8192
 
 
 def test_workspace_size_with_majorant_grid(lp):
@@ -93,9 +94,9 @@ def test_workspace_size_with_majorant_grid(lp):
     prm.majorant_grid = 16
     r, sz = call_generate(lp, vol, med, light, prm)
     # the 16^3 cell majorants (16 KiB) sit between the spatial orders and the brick copy
-    assert r == LF_OK and sz == 256 + 256 + 256 + 16384 + 4096
+    assert r == LF_OK and sz == 256 + 256 + 256 + 16384 + 8192
     prm.majorant = 2.0  # a fixed global majorant needs no grid
-    assert call_generate(lp, vol, med, light, prm)[1] == 256 + 256 + 256 + 4096
+    assert call_generate(lp, vol, med, light, prm)[1] == 256 + 256 + 256 + 8192
 
 
 def test_majorant_grid_rejects(lp):
@@ -115,6 +116,10 @@ def test_majorant_grid_rejects(lp):
     (lambda v, m, l, p: (setattr(v, "brick", 8), setattr(v, "nx", 12)), LF_E_ARG, "multiples of 8"),
     (lambda v, m, l, p: setattr(v, "brick", 4), LF_E_UNSUPPORTED, "brick"),
     (lambda v, m, l, p: setattr(v, "vmax", -1.0), LF_E_ARG, "vmax"),
+    (lambda v, m, l, p: setattr(v, "nx", 65536), LF_E_RANGE, "too large"),
+    # 2048^3: its halo-brick copy (683^3 bricks of 64 voxels) passes 2^32 voxels
+    (lambda v, m, l, p: (setattr(v, "nx", 2048), setattr(v, "ny", 2048), setattr(v, "nz", 2048)), LF_E_RANGE,
+     "too large"),
     (lambda v, m, l, p: setattr(m, "lut_size", 1), LF_E_ARG, "lut_size"),
     (lambda v, m, l, p: setattr(m, "lut", 0x20004), LF_E_ARG, "aligned"),
     (lambda v, m, l, p: (setattr(v, "type", 2), setattr(v, "data", 0x10002)), LF_E_ARG, "aligned"),
