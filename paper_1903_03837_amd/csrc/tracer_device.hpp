@@ -131,7 +131,7 @@ __device__ __forceinline__ void tile_coords(long long t, int tiles_i, int tiles_
 }
 
 // Lane states of the persistent kernels.
-enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4, kShadow2 = 5 };
+enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4, kShadow2 = 5, kScatter = 6 };
 
 // Next tile for a wave whose home part is `home`; -1 when all are taken.
 __device__ __forceinline__ long long next_tile(unsigned int* ctr, long long ntiles, int home, unsigned& dry) {

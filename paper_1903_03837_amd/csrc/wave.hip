@@ -6,13 +6,17 @@
 // one ray per lane and all of a ray's samples in a loop, a wave64 runs as
 // long as its most expensive lane; measured lane utilisation was 17 %.  Here
 // every lane runs its own state machine
-//     IDLE -> START -> FLIGHT <-> VERTEX -> SHADOW -> FLIGHT ... -> IDLE
+//     IDLE -> START -> FLIGHT -> VERTEX -> SHADOW -> SCATTER -> FLIGHT ... -> IDLE
 // and every loop iteration advances all lanes by one Philox4x32-10 block:
 //   START   pair 0 jitters the origin, pair 1 is the first tentative collision;
 //   FLIGHT  two tentative collisions (delta tracking; the majorant grid is
 //           walked from the current point to each of them);
 //   VERTEX  light sample and phase-function words (NEE set-up);
-//   SHADOW  two ratio-tracking steps towards the light.
+//   SHADOW  two ratio-tracking steps towards the light;
+//   SCATTER the new direction from the phase words, then as FLIGHT (pairs 0
+//           and 1 of the next segment's block 0).
+// START, SCATTER and VERTEX run one shared rotation and one shared clip, so
+// a wave that holds all three pays for each once.
 // Both tentative points of a block are fetched before either is classified,
 // so a lane keeps 16 voxel loads in flight.  A lane whose sample ends starts
 // the next sample of its ray in the next iteration; a lane whose ray is done
@@ -208,44 +212,23 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
         bool stepB = stepA;
         bool sample_done = false, after_shadow = false;
 
-        if (mode == kStart) {
-            cnt.samples++;
-            // light-field ray: origin on S (jittered); view ray: the eye
-            x = P.views ? po : O + po * P.R;
-            if (P.jitter && !P.views) {
-                const float rho = P.jit_rad * sqrtf(u01(r.x));
-                float sa, ca;
-                sincospif(2.0f * u01(r.y), &sa, &ca);
-                f3 t1, t2;
-                frame(po, t1, t2);
-                x = x + (t1 * (rho * ca) + t2 * (rho * sa));
-            }
-            dir = d0;
-            T = mk3(1.0f, 1.0f, 1.0f);
-            W = 1.0f;
-            L = mk3(0.0f, 0.0f, 0.0f);
-            float tn, tf;
-            if (clip_box(bmin, bmax, x, dir, tn, tf) && sigbar > 0.0f) {
-                t = tn;
-                tend = tf;
-                mode = kFlight;
-                stepB = true;  // pair 1 is the first tentative collision
-            } else {
-                L = L + T * env * W;
-                sample_done = true;
-            }
-        } else if (mode == kVertex) {
-            // next-event estimation set-up: light sample (pair 0), phase words (pair 1)
+        // --------------------------------------------------- segment set-up
+        // A sample's first segment (START), the segment after a scatter
+        // (SCATTER: b already advanced) and the shadow ray of a vertex
+        // (VERTEX) share one rotation (START's jitter disk, SCATTER's phase
+        // direction) and one clip against the box.
+        const bool seg = mode == kStart || mode == kScatter;
+        const bool shadow_ray = mode == kVertex && P.light_on;
+        f3 Le = mk3(0.0f, 0.0f, 0.0f);
+        float dist = 0.0f;
+        if (mode == kVertex) {
+            // next-event estimation: light sample (pair 0); phase words (pair 1) kept for the scatter
             up0 = u01(r.z);
             up1 = u01(r.w);
             if (P.light_on) {
-                f3 Le;
-                float te = 0.0f;
                 if (P.light_kind == 0) {
                     om = mk3(P.ldir[0], P.ldir[1], P.ldir[2]);
                     Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]);
-                    float a0, a1;
-                    if (clip_box(bmin, bmax, x, om, a0, a1)) te = a1;
                 } else {
                     const f3 yl = mk3(P.lcorner[0], P.lcorner[1], P.lcorner[2]) +
                                   mk3(P.le1[0], P.le1[1], P.le1[2]) * u01(r.x) +
@@ -253,15 +236,52 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     const f3 v = yl - x;
                     const float d2 = dot(v, v);
                     const float rinv = rsq(d2);
-                    const float dist = d2 * rinv;
+                    dist = d2 * rinv;
                     om = v * rinv;
                     const float cl = fmaxf(0.0f, -dot(mk3(P.lnrm[0], P.lnrm[1], P.lnrm[2]), om));
                     Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * (cl * P.larea * rcp(d2));
-                    float a0, a1;
-                    te = dist;
-                    if (clip_box(bmin, bmax, x, om, a0, a1)) te = fminf(te, a1);
-                    else te = 0.0f;
                 }
+            } else {
+                after_shadow = true;
+            }
+        } else if (seg) {
+            // base + A (cos(2 pi u) t1 + sin(2 pi u) t2), (t1, t2) completing n
+            f3 n, base;
+            float A, ua;
+            if (mode == kStart) {
+                cnt.samples++;
+                // light-field ray: origin on S (jittered); view ray: the eye
+                base = P.views ? po : O + po * P.R;
+                n = po;
+                A = (P.jitter && !P.views) ? P.jit_rad * sqrtf(u01(r.x)) : 0.0f;
+                ua = u01(r.y);
+                T = mk3(1.0f, 1.0f, 1.0f);
+                W = 1.0f;
+                L = mk3(0.0f, 0.0f, 0.0f);
+            } else {
+                const float mu = hg_mu(P.g, up0);
+                A = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+                base = dir * mu;
+                n = dir;
+                ua = up1;
+            }
+            float sa, ca;
+            sincospif(2.0f * ua, &sa, &ca);
+            f3 t1, t2;
+            frame(n, t1, t2);
+            const f3 v = base + t1 * (A * ca) + t2 * (A * sa);
+            if (mode == kStart) {
+                x = v;
+                dir = d0;
+            } else {
+                dir = v;
+            }
+        }
+        if (seg || shadow_ray) {
+            float tn, tf;
+            const bool hit = clip_box(bmin, bmax, x, shadow_ray ? om : dir, tn, tf);
+            if (shadow_ray) {
+                const float te = hit ? (P.light_kind == 0 ? tf : fminf(dist, tf)) : 0.0f;
                 C = T * Le * (W * hg_phase(P.g, dot(dir, om)));
                 Tr = 1.0f;
                 if (sigbar > 0.0f) {
@@ -273,8 +293,17 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     L = L + C;
                     after_shadow = true;
                 }
+            } else if (hit && sigbar > 0.0f) {
+                // START: pair 1 is the first tentative collision (pair 0 was the
+                // jitter); SCATTER: pairs 0 and 1
+                stepA = mode == kScatter;
+                stepB = true;
+                t = tn;
+                tend = tf;
+                mode = kFlight;
             } else {
-                after_shadow = true;
+                L = L + T * env * W;
+                sample_done = true;
             }
         }
 
@@ -391,28 +420,14 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
         }
 
         // ------------------------------------------------ scatter direction
+        // (drawn at the start of the next iteration, from the phase words)
         if (after_shadow) {
             if (b == P.maxb - 1) {
                 sample_done = true;
             } else {
-                const float mu = hg_mu(P.g, up0);
-                const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
-                float sp, cp;
-                sincospif(2.0f * up1, &sp, &cp);
-                f3 t1, t2;
-                frame(dir, t1, t2);
-                dir = t1 * (st * cp) + t2 * (st * sp) + dir * mu;
                 ++b;
-                float tn, tf;
-                if (clip_box(bmin, bmax, x, dir, tn, tf) && sigbar > 0.0f) {
-                    t = tn;
-                    tend = tf;
-                    mode = kFlight;
-                    blk = 0;
-                } else {
-                    L = L + T * env * W;
-                    sample_done = true;
-                }
+                blk = 0;
+                mode = kScatter;
             }
         }
 
