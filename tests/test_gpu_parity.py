@@ -271,6 +271,54 @@ def test_vacuum_and_linearity(lp):
     assert np.array_equal(b, 2 * a)
 
 
+def sf_chords(orc, M, N):
+    """FP64 SF origins on S and unit directions of every ray k = i*N + j."""
+    R = math.sqrt(3.0)
+    o = orc.sf_points(M) * R
+    d = orc.sf_points(N) * R
+    i, j = np.divmod(np.arange(M * N), N)
+    v = d[j] - o[i]
+    n = np.linalg.norm(v, axis=1, keepdims=True)
+    return o[i], v / np.where(n > 0, n, 1.0)
+
+
+def chord_misses(o, d, lo, hi):
+    """True where o + t d (t >= 0) misses the box [lo, hi]^3 (FP64 slabs)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1, t2 = (lo - o) / d, (hi - o) / d
+    tn = np.maximum(np.nanmax(np.minimum(t1, t2), axis=1), 0.0)
+    tf = np.nanmin(np.maximum(t1, t2), axis=1)
+    return ~(tn < tf)
+
+
+@pytest.mark.parametrize("jitter", [1, 0])
+def test_rays_missing_the_box(lp, orc, jitter):
+    """Rays whose every sample misses the volume box are finished at once:
+    each of them holds the FP32 sum of spp environment samples / spp, the
+    value the per-sample loop adds up.  Rays near the box's silhouette take
+    the per-sample path; all rays match the oracle.  (A box of half size, so
+    that about half of the chords miss it.)"""
+    M = N = 64
+    spp = 8
+    sc = S.config(1, M=M, N=N, spp=spp, jitter=jitter)
+    sc = sc.replace(volume=dataclasses.replace(sc.volume, box_min=(-0.5, -0.5, -0.5), box_max=(0.5, 0.5, 0.5)),
+                    light=dataclasses.replace(sc.light, env=(0.3, 0.2, 0.1)))
+    got = gpu_field(lp, sc)
+    o, d = sf_chords(orc, M, N)
+    pad = 2.0 * math.sqrt(3.0) / math.sqrt(M) * 1.01 + 1e-4 if jitter else 1e-4
+    miss = chord_misses(o, d, -0.5 - pad, 0.5 + pad)
+    ks = nondegenerate(M, N, np.arange(M * N))
+    miss_ks = ks[miss[ks]]
+    assert 0.2 * len(ks) < len(miss_ks) < 0.9 * len(ks)
+    acc = np.zeros(3, np.float32)
+    for _ in range(spp):
+        acc = acc + np.array([0.3, 0.2, 0.1], np.float32)
+    want = (acc / np.float32(spp)).astype(np.float64)
+    assert np.array_equal(got[miss_ks], np.broadcast_to(want, (len(miss_ks), 3)))
+    ref = orc.generate(sc, ks)
+    assert rel_l1(got[ks], ref) <= RAD_TOL
+
+
 @pytest.mark.parametrize("dtype,bound", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
 def test_half_storage(lp, orc, dtype, bound):
     """FP16/BF16 storage rounds the FP32 mean once (round to nearest even)."""
