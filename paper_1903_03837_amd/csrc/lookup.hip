@@ -53,9 +53,32 @@ __device__ __forceinline__ void sort_by_index(int* idx, float* w) {
         }
 }
 
+// DPP lane move (a v_mov_b32_dpp): lanes that the row / bank masks disable,
+// or whose source lies outside the row under bound_ctrl, read `old`.
+template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_CTRL>
+__device__ __forceinline__ float dpp(float old, float src) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, ROW_MASK, BANK_MASK, BOUND_CTRL));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), left in lane 63:
+// prefix sums of 4 inside each 16-lane row, then of 8 and 16 (row_shr), then
+// the rows joined by the row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+    float s = v + dpp<0x111, 0xf, 0xf, true>(0.0f, v);  // row_shr:1
+    s = s + dpp<0x112, 0xf, 0xf, true>(0.0f, v);        // row_shr:2
+    s = s + dpp<0x113, 0xf, 0xf, true>(0.0f, v);        // row_shr:3
+    s = s + dpp<0x114, 0xf, 0xe, false>(0.0f, s);       // row_shr:4, lanes 4..15 of each row
+    s = s + dpp<0x118, 0xf, 0xc, false>(0.0f, s);       // row_shr:8, lanes 8..15
+    s = s + dpp<0x142, 0xa, 0xf, false>(0.0f, s);       // row_bcast:15 into rows 1 and 3
+    s = s + dpp<0x143, 0xc, 0xf, false>(0.0f, s);       // row_bcast:31 into rows 2 and 3
+    return s;
+}
+
 // Wave-aggregated scatter-add of a 3-vector: lanes holding the same texel
-// are summed with cross-lane adds and one lane issues the three atomics.
+// are summed across the wave (DPP) and lane 63 issues the three atomics.
 // Each pass retires every lane whose key equals the first pending lane's.
+// Called with every lane of the wave active.
 __device__ __forceinline__ void wave_scatter_add(float* d_lf, bool pending, uint64_t key, f3 v) {
     const int lane = threadIdx.x & 63;
     uint64_t live = __ballot(pending);
@@ -63,14 +86,10 @@ __device__ __forceinline__ void wave_scatter_add(float* d_lf, bool pending, uint
         const int leader = __ffsll((long long)live) - 1;
         const uint64_t lk = __shfl(key, leader, 64);
         const bool mine = pending && key == lk;
-        float a = mine ? v.x : 0.0f, b = mine ? v.y : 0.0f, c = mine ? v.z : 0.0f;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            a += __shfl_xor(a, o, 64);
-            b += __shfl_xor(b, o, 64);
-            c += __shfl_xor(c, o, 64);
-        }
-        if (lane == leader) {
+        const float a = wave_sum_lane63(mine ? v.x : 0.0f);
+        const float b = wave_sum_lane63(mine ? v.y : 0.0f);
+        const float c = wave_sum_lane63(mine ? v.z : 0.0f);
+        if (lane == 63) {
             float* dl = d_lf + 3 * lk;
             atomicAdd(dl + 0, a);
             atomicAdd(dl + 1, b);
