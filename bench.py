@@ -402,7 +402,7 @@ def main():
             "K": K, "volume": "256^3 u16 linear", "majorant_grid": prm.grid,
         },
         "roofline": {
-            "kernel": "gen_kernel (lf_generate)",
+            "kernel": "gen_wave_kernel<u16, forward> (lf_generate)",
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_OPS / 1e12,
