@@ -22,14 +22,15 @@ hipError_t launch_zero(float* p, long long n, hipStream_t s) {
 // (bx, by, bz) holds the 4^3 voxels from (3 bx, 3 by, 3 bz), so neighbouring
 // bricks share a layer and every trilinear footprint lies in one brick.
 // Voxels past the last index repeat the edge (no valid footprint reads them).
+// One workgroup: 4 consecutive bricks along x, one lane per voxel (no
+// integer division: the grid is the brick grid).
 template <typename T>
-__global__ void halo_brick_kernel(const T* src, int layout, int nx, int ny, int nz, int nbx, int nby, long long total,
-                                  T* dst) {
-    const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= total) return;
-    const long long bk = d >> 6;
-    const int w = (int)(d & 63);
-    const int bx = (int)(bk % nbx), by = (int)((bk / nbx) % nby), bz = (int)(bk / ((long long)nbx * nby));
+__global__ __launch_bounds__(256) void halo_brick_kernel(const T* src, int layout, int nx, int ny, int nz, int nbx,
+                                                         int nby, T* dst) {
+    const int bx = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (bx >= nbx) return;
+    const int by = blockIdx.y, bz = blockIdx.z;
+    const int w = threadIdx.x & 63;
     const int x = min(bx * 3 + (w & 3), nx - 1), y = min(by * 3 + ((w >> 2) & 3), ny - 1),
               z = min(bz * 3 + (w >> 4), nz - 1);
     long long si;
@@ -39,23 +40,21 @@ __global__ void halo_brick_kernel(const T* src, int layout, int nx, int ny, int 
     } else {
         si = x + (long long)nx * (y + (long long)ny * z);
     }
-    dst[d] = src[si];
+    dst[(((long long)bz * nby + by) * nbx + bx) * 64 + w] = src[si];
 }
 
 hipError_t launch_halo_bricks(const void* src, int vtype, int layout, int nx, int ny, int nz, void* dst,
                               hipStream_t s) {
     const int nbx = halo_bricks(nx), nby = halo_bricks(ny), nbz = halo_bricks(nz);
-    const long long total = 64ll * nbx * nby * nbz;
-    const unsigned blocks = (unsigned)((total + 255) / 256);
+    const dim3 grid((unsigned)((nbx + 3) / 4), (unsigned)nby, (unsigned)nbz);
     if (vtype == 0)
-        halo_brick_kernel<uint8_t><<<blocks, 256, 0, s>>>((const uint8_t*)src, layout, nx, ny, nz, nbx, nby, total,
-                                                           (uint8_t*)dst);
+        halo_brick_kernel<uint8_t><<<grid, 256, 0, s>>>((const uint8_t*)src, layout, nx, ny, nz, nbx, nby,
+                                                         (uint8_t*)dst);
     else if (vtype == 1)
-        halo_brick_kernel<uint16_t><<<blocks, 256, 0, s>>>((const uint16_t*)src, layout, nx, ny, nz, nbx, nby,
-                                                            total, (uint16_t*)dst);
+        halo_brick_kernel<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)src, layout, nx, ny, nz, nbx, nby,
+                                                          (uint16_t*)dst);
     else
-        halo_brick_kernel<float><<<blocks, 256, 0, s>>>((const float*)src, layout, nx, ny, nz, nbx, nby, total,
-                                                         (float*)dst);
+        halo_brick_kernel<float><<<grid, 256, 0, s>>>((const float*)src, layout, nx, ny, nz, nbx, nby, (float*)dst);
     return hipGetLastError();
 }
 
@@ -87,18 +86,32 @@ __global__ __launch_bounds__(1024) void majorant_grid_kernel(const T* vol, int l
         cnt[a] = hi - lo[a] + 1;
     }
     float vlo = 3.402823466e38f, vhi = -3.402823466e38f;
-    const int total = cnt[0] * cnt[1] * cnt[2];
-    for (int e = threadIdx.x; e < total; e += 1024) {
-        const int x = lo[0] + e % cnt[0], y = lo[1] + (e / cnt[0]) % cnt[1], z = lo[2] + e / (cnt[0] * cnt[1]);
-        long long at;
-        if (layout == 8)
-            at = ((x >> 3) + (long long)(nx >> 3) * ((y >> 3) + (long long)(ny >> 3) * (z >> 3))) * 512 + (x & 7) +
-                 8 * ((y & 7) + 8 * (z & 7));
-        else
-            at = x + (long long)nx * (y + (long long)ny * z);
-        const float v = (float)vol[at];
-        vlo = fminf(vlo, v);
-        vhi = fmaxf(vhi, v);
+    // one wave per (y, z) row of the block, lanes along x; eight rows per
+    // trip so that eight loads are in flight
+    const int rows = cnt[1] * cnt[2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r0 = wave; r0 < rows; r0 += 16 * 8) {
+        for (int dx = lane; dx < cnt[0]; dx += 64) {
+            const int x = lo[0] + dx;
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int r = min(r0 + 16 * u, rows - 1);  // a repeated row changes no extreme
+                const int y = lo[1] + r % cnt[1], z = lo[2] + r / cnt[1];
+                long long at;
+                if (layout == 8)
+                    at = ((x >> 3) + (long long)(nx >> 3) * ((y >> 3) + (long long)(ny >> 3) * (z >> 3))) * 512 +
+                         (x & 7) + 8 * ((y & 7) + 8 * (z & 7));
+                else
+                    at = x + (long long)nx * (y + (long long)ny * z);
+                v[u] = (float)vol[at];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                vlo = fminf(vlo, v[u]);
+                vhi = fmaxf(vhi, v[u]);
+            }
+        }
     }
     rlo[threadIdx.x] = vlo;
     rhi[threadIdx.x] = vhi;
