@@ -4,9 +4,10 @@
 One step = one pass of the whole path over the CT-like workload (256^3 u16
 phantom, M = N = 2048 spherical-Fibonacci points, 4.19M rays, 64 samples per
 ray, 8 bounces, HG g = 0.3, area light):
-  lf_points (SF table) -> lf_generate (FP32 light field, 5^3 majorant grid) -> lf_lookup (32 views
-  of 1920 x 1080, K = 5) -> gradient of 1/2 |views - targets|^2 -> lf_lookup adjoint ->
-  lf_generate_backward (d LUT, d density scale).
+  lf_points (SF table) -> lf_generate (FP32 light field, 5^3 majorant grid, keeping
+  every sample's radiance) -> lf_lookup (32 views of 1920 x 1080, K = 5) -> gradient
+  of 1/2 |views - targets|^2 -> lf_lookup adjoint -> lf_generate_backward (d LUT,
+  d density scale; one replay per sample, from the kept radiance).
 `value` = M*N*spp path samples per second of the whole step.  One JSON line
 on stdout; progress on stderr.  Inputs are seeded synthetic data (lfsynth).
 """
@@ -191,7 +192,12 @@ def sweep_configs(configs, with_oracle=True, calib_copy_mb=0):
             img = lp.lookup(lf, prm, cams, W, H, sc.K)
             d_lf = lp.lookup_adjoint(img - target, prm, cams, sc.K)
             ms_bwd = timed(lambda: lp.generate_backward(vol, med, light, prm, d_lf), 5)
-            log(f"configs: c{c} adjoint {ms_bwd:.2f} ms")
+            # the same adjoint from the radiance a forward kept
+            srad = torch.empty((M, N, spp, 3), dtype=torch.float32, device=dev)
+            ms_keep = timed(lambda: lp.generate(vol, med, light, prm, out=lf, sample_radiance=srad), 5)
+            ms_bwd_keep = timed(lambda: lp.generate_backward(vol, med, light, prm, d_lf, sample_radiance=srad), 5)
+            del srad
+            log(f"configs: c{c} adjoint {ms_bwd:.2f} ms; keeping samples: forward {ms_keep:.2f}, adjoint {ms_bwd_keep:.2f} ms")
             d_lut, d_scale = lp.generate_backward(vol, med, light, prm, d_lf)
             torch.cuda.synchronize()
             g = np.concatenate([d_lut.cpu().numpy().reshape(-1), d_scale.cpu().numpy()]).astype(np.float64)
@@ -220,6 +226,8 @@ def sweep_configs(configs, with_oracle=True, calib_copy_mb=0):
             fd, gv = np.array(fd), np.array(gv)
             row["adjoint"] = {"views": len(cams), "width": W, "height": H, "backward_ms": ms_bwd,
                               "adjoint_forward_ratio": ms_bwd / ms,
+                              "kept_samples": {"forward_ms": ms_keep, "backward_ms": ms_bwd_keep,
+                                               "adjoint_forward_ratio": ms_bwd_keep / ms_keep},
                               "vs_central_differences_h1e-3": float(np.linalg.norm(gv - fd) / np.linalg.norm(fd)),
                               "fd_coordinates": len(fd)}
             if with_oracle:
@@ -283,6 +291,8 @@ def main():
     img = torch.empty((V, H, W, 3), dtype=torch.float32, device=dev)
     dimg = torch.empty_like(img)
     d_lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
+    # every sample's radiance, kept by the forward for the adjoint (3.2 GB)
+    srad = torch.empty((M, N, spp, 3), dtype=torch.float32, device=dev)
 
     # seeded target views: the same scene under the perturbed medium
     tm = S.target_medium(sc)
@@ -305,7 +315,7 @@ def main():
         evs[0].record(stream)
         lp.points(M)
         evs[1].record(stream)
-        lp.generate(vol, med, light, prm, out=lf)
+        lp.generate(vol, med, light, prm, out=lf, sample_radiance=srad)
         evs[2].record(stream)
         lp.lookup(lf, prm, cams, W, H, K, img=img)
         evs[3].record(stream)
@@ -315,7 +325,7 @@ def main():
         d_lf.zero_()
         lp.lookup_adjoint(dimg, prm, cams, K, d_lf=d_lf)
         evs[5].record(stream)
-        d_lut, d_scale = lp.generate_backward(vol, med, light, prm, d_lf)
+        d_lut, d_scale = lp.generate_backward(vol, med, light, prm, d_lf, sample_radiance=srad)
         evs[6].record(stream)
         return d_lut, d_scale
 
@@ -397,7 +407,7 @@ def main():
         "config": {
             "workload": "CT-like phantom 256^3 u16 (12 nested ellipsoids), M=N=2048 SF points (4.19M rays), "
                         "64 spp, 8 bounces, HG g=0.3, area light, 5^3 majorant grid, FP32 light field; lookup of "
-                        "32 views 1920x1080 K=5; adjoint of the loss 1/2 |views - targets|^2",
+                        "32 views 1920x1080 K=5; adjoint of the loss 1/2 |views - targets|^2 by path replay from the forward's per-sample radiance",
             "M": M, "N": N, "spp": spp, "max_bounces": prm.max_bounces, "views": V, "width": W, "height": H,
             "K": K, "volume": "256^3 u16 linear", "majorant_grid": prm.grid,
         },

@@ -126,7 +126,14 @@ typedef struct {
  * and cosine-weighted bounces (pair 1); normals are central differences over
  * a quarter voxel.  The majorant grid size (8 when 0) sets the cells whose
  * raw ranges let the march skip fetches.  Frozen sampling and
- * lf_generate_backward are not available in this variant (LF_E_UNSUPPORTED). */
+ * lf_generate_backward are not available in this variant (LF_E_UNSUPPORTED).
+ * sample_radiance (light-field calls only; NULL in the isosurface variant):
+ * lf_generate writes the radiance of every sample of every generated ray
+ * at ((i*N + j)*spp + s)*3 (texels i == j are not written, and of a ray
+ * that misses the volume box in every sample only the last sample is);
+ * lf_generate_backward reads it instead of tracing each sample a first
+ * time.  It must come from lf_generate with the same parameters and medium
+ * and sample == NULL. */
 typedef struct {
     int32_t M, N;
     float center[3];
@@ -142,6 +149,7 @@ typedef struct {
     uint64_t* stats;
     int32_t surface;        /* 1: isosurface variant at raw value iso */
     float iso;
+    float* sample_radiance; /* NULL or device float32 [origin_rows][N][spp][3] */
 } lf_gen_params;
 
 /* Pinhole view (host array): pixel (x, y) looks through its centre, row 0 at
@@ -244,7 +252,8 @@ int lf_majorant_grid(const lf_volume* vol, const lf_medium* sample, const lf_gen
  * (float32 [1]) with d(loss)/d(LUT) and d(loss)/d(density_scale) of the
  * estimator for the same random stream, majorant held fixed.  Each sample is
  * traced twice (total radiance, then scores times radiance gathered after
- * each event); nothing is stored per path.  Accumulation uses float atomics:
+ * each event); nothing is stored per path.  With params->sample_radiance
+ * (the samples' radiance kept by lf_generate) the first trace is skipped.  Accumulation uses float atomics:
  * reproducible to rounding only.  Rows with zero adjoint are skipped.
  * Workspace as for lf_generate. */
 int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf_light* light,

@@ -66,7 +66,7 @@ class _GenParams(C.Structure):
                 ("majorant_grid", C.c_int32),
                 ("seed", C.c_uint64), ("jitter", C.c_int32), ("origin_rows", C.c_int32),
                 ("row_begin", C.c_int64), ("row_end", C.c_int64), ("stats", C.c_void_p),
-                ("surface", C.c_int32), ("iso", C.c_float)]
+                ("surface", C.c_int32), ("iso", C.c_float), ("sample_radiance", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -216,7 +216,7 @@ class GenParams:
     def rows(self) -> int:
         return self.origin_rows if self.origin_rows > 0 else self.M
 
-    def c(self, stats: Optional[torch.Tensor] = None) -> _GenParams:
+    def c(self, stats: Optional[torch.Tensor] = None, sample_radiance: Optional[torch.Tensor] = None) -> _GenParams:
         s = _GenParams()
         s.M, s.N = self.M, self.N
         s.center[:] = [float(x) for x in self.center]
@@ -232,6 +232,9 @@ class GenParams:
         if stats is not None:
             _need(stats, 5, torch.int64, "stats")
         s.stats = _ptr(stats).value if stats is not None else None
+        if sample_radiance is not None:
+            _need(sample_radiance, self.rows * self.N * self.spp * 3, torch.float32, "sample_radiance")
+        s.sample_radiance = _ptr(sample_radiance).value if sample_radiance is not None else None
         return s
 
 
@@ -301,15 +304,17 @@ def _workspace(fn, *args) -> torch.Tensor:
 
 def generate(vol: Volume, med: Medium, light: Light, prm: GenParams, dtype: str = "f32",
              sample: Optional[Medium] = None, out: Optional[torch.Tensor] = None,
-             stats: Optional[torch.Tensor] = None) -> torch.Tensor:
+             stats: Optional[torch.Tensor] = None, sample_radiance: Optional[torch.Tensor] = None) -> torch.Tensor:
     """lf_generate: light field [rows, N, 3] of `dtype` ('f32', 'f16', 'bf16'),
-    rows = prm.origin_rows or M."""
+    rows = prm.origin_rows or M.  sample_radiance: None or float32
+    [rows, N, spp, 3] that receives every sample's radiance (for
+    generate_backward)."""
     dt = DTYPES[dtype]
     if out is None:
         out = torch.empty((prm.rows, prm.N, 3), dtype=_TORCH_DTYPE[dt], device=vol.data.device)
     _need(out, prm.rows * prm.N * 3, _TORCH_DTYPE[dt], "out")
     L = library()
-    v, m, l, p = vol.c(), med.c(), light.c(), prm.c(stats)
+    v, m, l, p = vol.c(), med.c(), light.c(), prm.c(stats, sample_radiance)
     s = sample.c() if sample is not None else None
     args = [C.byref(v), C.byref(m), C.byref(s) if s is not None else None, C.byref(l), C.byref(p), dt,
             _ptr(out)]
@@ -361,14 +366,17 @@ def majorant_grid(vol: Volume, med: Medium, prm: GenParams) -> torch.Tensor:
     return out
 
 
-def generate_backward(vol: Volume, med: Medium, light: Light, prm: GenParams, d_lf: torch.Tensor):
-    """lf_generate_backward: (d_lut [L,4], d_scale [1]) for d(loss)/d(Lhat)."""
+def generate_backward(vol: Volume, med: Medium, light: Light, prm: GenParams, d_lf: torch.Tensor,
+                      sample_radiance: Optional[torch.Tensor] = None):
+    """lf_generate_backward: (d_lut [L,4], d_scale [1]) for d(loss)/d(Lhat).
+    sample_radiance: None, or the per-sample radiance that generate() kept
+    with the same parameters and medium (the first replay pass is skipped)."""
     d_lf = d_lf.contiguous().float()
     _need(d_lf, prm.rows * prm.N * 3, torch.float32, "d_lf")
     d_lut = torch.empty_like(med.lut)
     d_scale = torch.empty(1, dtype=torch.float32, device=med.lut.device)
     L = library()
-    v, m, l, p = vol.c(), med.c(), light.c(), prm.c()
+    v, m, l, p = vol.c(), med.c(), light.c(), prm.c(sample_radiance=sample_radiance)
     args = [C.byref(v), C.byref(m), C.byref(l), C.byref(p), _ptr(d_lf), _ptr(d_lut), _ptr(d_scale)]
     ws, sz = _workspace(L.lf_generate_backward, *args)
     _check(L.lf_generate_backward(*args, _ptr(ws), C.byref(sz), _stream()))
@@ -412,21 +420,27 @@ def lookup_adjoint(dimg: torch.Tensor, prm: GenParams, cams: Sequence[Camera], K
 # ----------------------------------------------------------------- autograd
 class LightFieldFn(torch.autograd.Function):
     """Lhat = generate(LUT, density scale); backward by path replay
-    (lf_generate_backward).  `scale` is a 0-d float tensor on the CPU."""
+    (lf_generate_backward).  `scale` is a 0-d float tensor on the CPU.  With
+    keep_samples the forward keeps every sample's radiance (rows x N x spp x
+    12 bytes) so that the backward traces each sample once instead of twice."""
 
     @staticmethod
-    def forward(ctx, lut, scale, vol, light, prm):
+    def forward(ctx, lut, scale, vol, light, prm, keep_samples=False):
         med = Medium(lut.detach().contiguous(), float(scale))
         ctx.vol, ctx.light, ctx.prm = vol, light, prm
         ctx.save_for_backward(lut, scale)
-        return generate(vol, med, light, prm)
+        ctx.srad = None
+        if keep_samples:
+            ctx.srad = torch.empty((prm.rows, prm.N, prm.spp, 3), dtype=torch.float32, device=lut.device)
+        return generate(vol, med, light, prm, sample_radiance=ctx.srad)
 
     @staticmethod
     def backward(ctx, g):
         lut, scale = ctx.saved_tensors
         d_lut, d_scale = generate_backward(ctx.vol, Medium(lut.detach().contiguous(), float(scale)), ctx.light,
-                                           ctx.prm, g)
-        return d_lut, d_scale.to(scale.device).reshape(scale.shape), None, None, None
+                                           ctx.prm, g, sample_radiance=ctx.srad)
+        ctx.srad = None
+        return d_lut, d_scale.to(scale.device).reshape(scale.shape), None, None, None, None
 
 
 class LookupFn(torch.autograd.Function):

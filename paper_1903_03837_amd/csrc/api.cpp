@@ -82,6 +82,9 @@ int check_params(const lf_gen_params* p, bool need_rays) {
         return fail(LF_E_ARG, "majorant_grid must be in [0, 16] (got %d)", p->majorant_grid);
     if (p->surface != 0 && p->surface != 1) return fail(LF_E_ARG, "surface must be 0 or 1");
     if (!std::isfinite(p->iso)) return fail(LF_E_ARG, "iso must be finite");
+    if (p->sample_radiance && p->surface)
+        return fail(LF_E_UNSUPPORTED, "sample_radiance is not available in the isosurface variant");
+    if ((uintptr_t)p->sample_radiance % 4) return fail(LF_E_ARG, "sample_radiance is not aligned to 4 bytes");
     const long long rows = p->origin_rows > 0 ? p->origin_rows : p->M;
     const long long re = p->row_end <= 0 ? rows : p->row_end;
     if (p->row_begin < 0 || p->row_begin > re || re > rows)
@@ -97,8 +100,6 @@ int check_volume(const lf_volume* v) {
     if (v->nx > 65535 || v->ny > 65535 || v->nz > 65535 || brick_voxels(v) > 0xFFFFFFFFull)
         return fail(LF_E_RANGE, "volume too large: its halo-brick copy (%zu voxels) needs 32-bit voxel indices",
                     brick_voxels(v));
-    if (64ull * ((v->nx + 3) / 4) * ((v->ny + 3) / 4) * ((v->nz + 3) / 4) >= (1ull << 32))
-        return fail(LF_E_RANGE, "volume too large");
     const uintptr_t esz = v->type == LF_VOX_U8 ? 1 : (v->type == LF_VOX_U16 ? 2 : 4);
     if ((uintptr_t)v->data % esz) return fail(LF_E_ARG, "volume data is not aligned to its voxel size");
     if (v->brick != 0 && v->brick != 8) return fail(LF_E_UNSUPPORTED, "brick must be 0 or 8");
@@ -203,6 +204,7 @@ void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, cons
     T.row_begin = (int32_t)p->row_begin;
     T.row_end = (int32_t)(p->row_end <= 0 ? stored_rows(p) : p->row_end);
     T.stats = (unsigned long long*)p->stats;
+    T.srad = p->sample_radiance;
     const int G = grid_cells(p);
     T.grid_n = G > 0 ? G : 1;
     for (int a = 0; a < 3; ++a) {
@@ -415,6 +417,7 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
     // the tracer set-up of lf_generate with a one-point ray set, then the views
     lf_gen_params p1 = *params;
     p1.M = p1.N = 1;
+    p1.sample_radiance = nullptr;
     p1.origin_rows = 0;
     p1.row_begin = 0;
     p1.row_end = 1;

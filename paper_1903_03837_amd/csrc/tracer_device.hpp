@@ -81,6 +81,9 @@ struct TraceParams {
     void* out;
     int32_t dtype;
     unsigned long long* stats;
+    // per-sample radiance [rows][N][spp][3]: written by the forward,
+    // read by the adjoint in place of its first pass (or NULL)
+    float* srad;
     // adjoint
     const float* d_lf;
     float* d_lut;

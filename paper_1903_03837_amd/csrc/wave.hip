@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         j = (int)(kk - (uint32_t)i * (uint32_t)P.N);
                         const float* a = P.d_lf + 3 * (uint64_t)kk;
                         adj = mk3(a[0] * inv_spp, a[1] * inv_spp, a[2] * inv_spp);
-                        pass = 0;
+                        pass = P.srad ? 1 : 0;
                     }
                 } else if (P.views) {
                     // pixel of an 8 x 8 tile of a view: the ray from the eye through its centre
@@ -250,6 +250,12 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
             float A, ua;
             if (mode == kStart) {
                 cnt.samples++;
+                if constexpr (MODE == kGrad) {
+                    if (P.srad) {  // the sample's total radiance, kept by the forward
+                        const float* lt = P.srad + 3 * ((uint64_t)k * (uint32_t)P.spp + (uint32_t)s);
+                        ltot = mk3(lt[0], lt[1], lt[2]);
+                    }
+                }
                 // light-field ray: origin on S (jittered); view ray: the eye
                 base = P.views ? po : O + po * P.R;
                 n = po;
@@ -440,10 +446,16 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     pass = 1;
                     next = false;
                 } else {
-                    pass = 0;
+                    pass = P.srad ? 1 : 0;
                 }
             } else {
                 acc = acc + L;
+                if (P.srad && !P.views) {
+                    float* o = P.srad + 3 * ((uint64_t)k * (uint32_t)P.spp + (uint32_t)s);
+                    o[0] = L.x;
+                    o[1] = L.y;
+                    o[2] = L.z;
+                }
             }
             if (next && ++s == P.spp) {
                 if constexpr (MODE != kGrad) {

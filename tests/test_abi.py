@@ -47,7 +47,7 @@ def test_struct_layouts_match_header(lp):
     assert C.sizeof(lp._Volume) == 64
     assert C.sizeof(lp._Medium) == 16
     assert C.sizeof(lp._Light) == 76
-    assert C.sizeof(lp._GenParams) == 96
+    assert C.sizeof(lp._GenParams) == 104
     assert C.sizeof(lp._Camera) == 40
 
 
@@ -144,6 +144,15 @@ def test_generate_rejects(lp, mutate, code, msg):
     r, _ = call_generate(lp, vol, med, light, prm)
     assert r == code
     assert msg in err(lp)
+
+
+def test_sample_radiance_rejects(lp):
+    vol, med, light, prm = scene(lp)
+    prm.sample_radiance = 0x10002
+    assert call_generate(lp, vol, med, light, prm)[0] == LF_E_ARG and "aligned" in err(lp)
+    prm.sample_radiance = 0x10000
+    prm.surface = 1
+    assert call_generate(lp, vol, med, light, prm)[0] == LF_E_UNSUPPORTED
 
 
 def test_generate_rejects_dtype_and_output(lp):

@@ -527,6 +527,37 @@ def test_backward_matches_oracle_gradient(lp, orc):
     assert abs(float(d_scale[0]) - o_scale) <= 1e-3 * abs(o_scale)
 
 
+def test_backward_from_stored_sample_radiance(lp, orc):
+    """generate() keeps each sample's radiance (their in-order FP32 mean is
+    the field); generate_backward() given that buffer skips its first pass
+    and returns the same gradient."""
+    sc = grad_scene()
+    M = N = 48
+    spp = sc.params.spp
+    vol, med, light, prm, _ = lp.device_scene(sc)
+    srad = torch.full((M, N, spp, 3), float("nan"), dtype=torch.float32, device="cuda")
+    lf = lp.generate(vol, med, light, prm, sample_radiance=srad)
+    torch.cuda.synchronize()
+    field = lf.reshape(-1, 3).cpu().numpy()
+    sr = srad.reshape(M * N, spp, 3).cpu().numpy()
+    written = ~np.isnan(sr[:, 0, 0])
+    assert written.sum() > 0.5 * M * N
+    acc = np.zeros((M * N, 3), np.float32)
+    for s_ in range(spp):
+        acc = acc + sr[:, s_]
+    assert np.array_equal((acc / np.float32(spp))[written], field[written])
+    rng = np.random.default_rng(15)
+    adj = rng.standard_normal((M * N, 3)).astype(np.float32)
+    adj[np.arange(M) * (N + 1)] = 0.0
+    d = torch.from_numpy(adj).cuda()
+    a_lut, a_s = lp.generate_backward(vol, med, light, prm, d)
+    b_lut, b_s = lp.generate_backward(vol, med, light, prm, d, sample_radiance=srad)
+    torch.cuda.synchronize()
+    a = np.concatenate([a_lut.cpu().numpy().reshape(-1), a_s.cpu().numpy()]).astype(np.float64)
+    b = np.concatenate([b_lut.cpu().numpy().reshape(-1), b_s.cpu().numpy()]).astype(np.float64)
+    assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a)
+
+
 def test_backward_matches_finite_differences(lp, orc):
     """Central differences (h = 1e-3) of the GPU forward in frozen sampling."""
     sc = grad_scene()
@@ -601,10 +632,12 @@ def test_backward_with_grid_matches_finite_differences(lp, orc):
     assert err <= 1e-2
 
 
-def test_autograd_pipeline(lp, orc):
+@pytest.mark.parametrize("keep_samples", [False, True])
+def test_autograd_pipeline(lp, orc, keep_samples):
     """Differentiation workload, reduced: LightFieldFn -> LookupFn -> L2 loss;
     the LUT gradient equals the oracle's chain (lookup transpose, then the
-    path-replay gradient) on the same views."""
+    path-replay gradient) on the same views, with the adjoint tracing each
+    sample twice or reading the radiance the forward kept."""
     M = N = 64
     V, W, H, K = 3, 48, 40, 5
     sc = S.config(5, M=M, N=N, spp=8, views=V, width=W, height=H)
@@ -620,7 +653,7 @@ def test_autograd_pipeline(lp, orc):
     target[flat] = t_rgb
     lut = med.lut.clone().requires_grad_(True)
     scale = torch.tensor(float(med.scale), requires_grad=True)
-    lf = lp.LightFieldFn.apply(lut, scale, vol, light, prm)
+    lf = lp.LightFieldFn.apply(lut, scale, vol, light, prm, keep_samples)
     img = lp.LookupFn.apply(lf, prm, cams, W, H, K)
     loss = ((img - torch.from_numpy(target.reshape(V, H, W, 3)).cuda()) ** 2).sum()
     loss.backward()
