@@ -210,32 +210,37 @@ __device__ __forceinline__ int sf_nearest(int n, float inv_n, const Pts& pts, f3
     return c;
 }
 
-// Keep the K nearest candidates in (distance^2, index) order.  Fully
-// unrolled rank selection so every array stays in registers.
+// Keep the K nearest candidates in (distance^2, index) order.  A squared
+// distance is a non-negative float, so its bits order like the value: each
+// candidate becomes one 64-bit key (d2 bits, index), and keys compare in
+// (distance, index) order with one unsigned comparison.  Nine rounds of
+// odd-even transposition sort the nine keys (registers only).
 template <int KMAX>
 __device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, float* out_d2) {
-    int rank[9];
+    uint64_t key[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        int r = 0;
+    for (int a = 0; a < 9; ++a) key[a] = ((uint64_t)__float_as_uint(C.d2[a]) << 32) | (uint32_t)C.idx[a];
+    if constexpr (KMAX == 1) {
 #pragma unroll
-        for (int b = 0; b < 9; ++b) r += (b != a) && closer(C.d2[b], C.idx[b], C.d2[a], C.idx[a]);
-        rank[a] = r;
+        for (int a = 1; a < 9; ++a) key[0] = key[a] < key[0] ? key[a] : key[0];
+    } else {
+#pragma unroll
+        for (int p = 0; p < 9; ++p)
+#pragma unroll
+            for (int a = (p & 1); a + 1 < 9; a += 2) {
+                const uint64_t lo = key[a] < key[a + 1] ? key[a] : key[a + 1];
+                const uint64_t hi = key[a] < key[a + 1] ? key[a + 1] : key[a];
+                key[a] = lo;
+                key[a + 1] = hi;
+            }
     }
     int cnt = 0;
 #pragma unroll
     for (int r = 0; r < KMAX; ++r) {
-        int id = -1;
-        float d = 3.402823466e38f;
-#pragma unroll
-        for (int a = 0; a < 9; ++a)
-            if (rank[a] == r) {
-                id = C.idx[a];
-                d = C.d2[a];
-            }
+        const int id = (int)(uint32_t)key[r];
         const bool ok = r < K && id >= 0 && id < 0x7fffff00;
         out_idx[r] = ok ? id : -1;
-        out_d2[r] = d;
+        out_d2[r] = __uint_as_float((uint32_t)(key[r] >> 32));
         cnt += ok;
     }
     return cnt;
