@@ -46,8 +46,8 @@ size_t brick_copy_bytes(const lf_volume* v) {
 
 // lf_generate workspace: majorant (offset 0), 8 tile counters (offset 64),
 // spatial order of the generated origin rows (offset 256), spatial order of
-// the directions, the cell majorants of the grid (when used), then the brick
-// copy of the volume.
+// the directions, the cell majorants of the grid (when used), the point
+// tables of both SF sets, then the brick copy of the volume.
 long long stored_rows(const lf_gen_params* p) { return p->origin_rows > 0 ? p->origin_rows : p->M; }
 
 // Cells per axis of the majorant grid in use (0: the global majorant).
@@ -59,9 +59,13 @@ size_t gen_perm_bytes(const lf_gen_params* p) {
     return 256 + align256(4 * rows) + align256(4 * (size_t)p->N);
 }
 
-size_t gen_order_bytes(const lf_gen_params* p) {
+size_t gen_grid_bytes(const lf_gen_params* p) {
     const size_t G = (size_t)grid_cells(p);
-    return gen_perm_bytes(p) + align256(4 * G * G * G);
+    return align256(4 * G * G * G);
+}
+
+size_t gen_order_bytes(const lf_gen_params* p) {
+    return gen_perm_bytes(p) + gen_grid_bytes(p) + align256(16 * (size_t)p->M) + align256(16 * (size_t)p->N);
 }
 
 int check_params(const lf_gen_params* p, bool need_rays) {
@@ -271,8 +275,14 @@ hipError_t setup_tracking(lp::TraceParams& T, const lf_volume* vol, const lf_med
     T.perm_o = perm_o;
     T.perm_d = perm_d;
     T.maj = sig;
+    float4* tab_o = (float4*)(w + gen_perm_bytes(p) + gen_grid_bytes(p));
+    float4* tab_d = (float4*)((char*)tab_o + align256(16 * (size_t)p->M));
+    T.tab_o = tab_o;
+    T.tab_d = tab_d;
     hipError_t e = lp::launch_wave_setup(T, sm->lut, sm->lut_size, sm->density_scale, p->majorant, sig, ctr,
                                          perm_o, perm_d, s);
+    if (e == hipSuccess) e = lp::launch_sf_table(p->M, 1.0f / (float)p->M, tab_o, s);
+    if (e == hipSuccess) e = lp::launch_sf_table(p->N, 1.0f / (float)p->N, tab_d, s);
     if (e == hipSuccess && grid_cells(p) > 0) {
         float* cells = (float*)(w + gen_perm_bytes(p));
         T.maj = cells;

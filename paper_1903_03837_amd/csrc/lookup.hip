@@ -309,10 +309,14 @@ __global__ void sf_table_kernel(int n, float inv_n, float4* t) {
     t[i] = make_float4(p.x, p.y, p.z, 0.0f);
 }
 
-hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s) {
-    sf_table_kernel<<<(P.M + 255) / 256, 256, 0, s>>>(P.M, P.invM, (float4*)P.tab_o);
-    sf_table_kernel<<<(P.N + 255) / 256, 256, 0, s>>>(P.N, P.invN, (float4*)P.tab_d);
+hipError_t launch_sf_table(int n, float inv_n, float4* out, hipStream_t s) {
+    sf_table_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, inv_n, out);
     return hipGetLastError();
+}
+
+hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s) {
+    hipError_t e = launch_sf_table(P.M, P.invM, (float4*)P.tab_o, s);
+    return e == hipSuccess ? launch_sf_table(P.N, P.invN, (float4*)P.tab_d, s) : e;
 }
 
 hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s) {

@@ -81,6 +81,10 @@ struct TraceParams {
     void* out;
     int32_t dtype;
     unsigned long long* stats;
+    // SF points of both sets (workspace tables filled by sf_point with
+    // inv_n = 1/n in FP32, the values the kernel would compute)
+    const float4* tab_o;
+    const float4* tab_d;
     // per-sample radiance [rows][N][spp][3]: written by the forward,
     // read by the adjoint in place of its first pass (or NULL)
     float* srad;

@@ -76,7 +76,6 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                                          : (long long)tiles_i * tiles_j;
     const int home = blockIdx.x % kParts;
     const float inv_spp = 1.0f / (float)P.spp;
-    const float invM = 1.0f / (float)P.M, invN = 1.0f / (float)P.N;
     const f3 O = mk3(P.O[0], P.O[1], P.O[2]);
     const f3 env = mk3(P.env[0], P.env[1], P.env[2]);
     const f3 bmin = mk3(P.bmin[0], P.bmin[1], P.bmin[2]), bmax = mk3(P.bmax[0], P.bmax[1], P.bmax[2]);
@@ -178,8 +177,9 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         // no direction: texel 0 (never listed for the adjoint)
                         if constexpr (MODE != kGrad) store_texel(P.out, P.dtype, k, mk3(0.0f, 0.0f, 0.0f));
                     } else {
-                        po = sf_point(P.M, i, invM);
-                        d0 = normalize(sf_point(P.N, j, invN) - po);
+                        const float4 a = P.tab_o[i], c = P.tab_d[j];
+                        po = mk3(a.x, a.y, a.z);
+                        d0 = normalize(mk3(c.x, c.y, c.z) - po);
                         acc = mk3(0.0f, 0.0f, 0.0f);
                         s = 0;
                         b = 0;
@@ -536,8 +536,9 @@ __global__ void active_rays_kernel(TraceParams P) {
                 const float* a = P.d_lf + 3 * (uint64_t)k;
                 take = !(P.M == P.N && i == j) && (a[0] != 0.0f || a[1] != 0.0f || a[2] != 0.0f);
                 if (take) {
-                    const f3 po = sf_point(P.M, i, 1.0f / (float)P.M);
-                    const f3 d0 = normalize(sf_point(P.N, j, 1.0f / (float)P.N) - po);
+                    const float4 a = P.tab_o[i], c = P.tab_d[j];
+                    const f3 po = mk3(a.x, a.y, a.z);
+                    const f3 d0 = normalize(mk3(c.x, c.y, c.z) - po);
                     take = !misses_box(P, mk3(P.O[0], P.O[1], P.O[2]), mk3(P.bmin[0], P.bmin[1], P.bmin[2]),
                                        mk3(P.bmax[0], P.bmax[1], P.bmax[2]), po, d0);
                 }

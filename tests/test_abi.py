@@ -84,19 +84,20 @@ def test_workspace_size_query(lp):
     vol, med, light, prm = scene(lp)
     r, sz = call_generate(lp, vol, med, light, prm)
     # majorant + counters, the spatial orders of 64 origins and 64 directions,
-    # then the halo-brick copy of the 16^3 u8 volume: 5^3 bricks of 64 voxels
-    # (8000 B, rounded up to 256 B)
-    assert r == LF_OK and sz == 256 + 256 + 256 + 8192
+    # the point tables of both SF sets (16 B per point), then the halo-brick
+    # copy of the 16^3 u8 volume: 5^3 bricks of 64 voxels (8000 B, rounded up
+    # to 256 B)
+    assert r == LF_OK and sz == 256 + 256 + 256 + 2048 + 8192
 
 
 def test_workspace_size_with_majorant_grid(lp):
     vol, med, light, prm = scene(lp)
     prm.majorant_grid = 16
     r, sz = call_generate(lp, vol, med, light, prm)
-    # the 16^3 cell majorants (16 KiB) sit between the spatial orders and the brick copy
-    assert r == LF_OK and sz == 256 + 256 + 256 + 16384 + 8192
+    # the 16^3 cell majorants (16 KiB) sit between the spatial orders and the point tables
+    assert r == LF_OK and sz == 256 + 256 + 256 + 16384 + 2048 + 8192
     prm.majorant = 2.0  # a fixed global majorant needs no grid
-    assert call_generate(lp, vol, med, light, prm)[1] == 256 + 256 + 256 + 8192
+    assert call_generate(lp, vol, med, light, prm)[1] == 256 + 256 + 256 + 2048 + 8192
 
 
 def test_majorant_grid_rejects(lp):
