@@ -177,17 +177,23 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
         }
 }
 
-template <int KMAX, int DT, int MODE>
+// Adjoint: every lane of the wave takes part in the aggregated scatter (no
+// early exit).  8 waves per SIMD (64 VGPRs, a few values spilled) ran 3 %
+// faster than 7 waves with no spills.
+template <int KMAX>
+__global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    lookup_adjoint_pixel<KMAX>(P, px, py, blockIdx.z);
+}
+
+template <int KMAX, int DT>
 __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int v = blockIdx.z;
-    if constexpr (MODE == 1) {
-        // adjoint: every lane of the wave takes part in the aggregated scatter
-        lookup_adjoint_pixel<KMAX>(P, px, py, v);
-        return;
-    }
     if (px >= P.W || py >= P.H) return;
     const ViewGeom& G = P.v[v];
     const uint64_t pix = ((uint64_t)(P.view0 + v) * P.H + py) * P.W + px;
@@ -201,7 +207,7 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
     const float b = dot(d, oc);
     const float disc = b * b - G.c;
     if (!(disc > P.thr)) {
-        if constexpr (MODE == 0) {
+        {
             float* o = P.img + 3 * pix;
             o[0] = o[1] = o[2] = 0.0f;
         }
@@ -237,7 +243,7 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
     if constexpr (KMAX == 1) {
         const bool covered = ia[0] < P.orows;
         const uint64_t t = (uint64_t)(covered ? ia[0] : 0) * (uint64_t)P.N + (uint64_t)jb[0];
-        if constexpr (MODE == 0) {
+        {
             const f3 c = covered ? load_texel<DT>(P.lf, t) : mk3(0.0f, 0.0f, 0.0f);
             float* o = P.img + 3 * pix;
             o[0] = c.x;
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
             const bool bad = P.degenerate && ia[a] == jb[c];
             wsum += bad ? 0.0f : wa[a] * wb[c];
         }
-    if constexpr (MODE == 0) {
+    {
         f3 acc = mk3(0.0f, 0.0f, 0.0f);
         if (wsum > 0.0f) {
             const float inv = 1.0f / wsum;
@@ -287,13 +293,14 @@ __global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
 template <int KMAX, int DT>
 static hipError_t launch_lookup_mode(const LookupParams& P, int mode, hipStream_t s) {
     dim3 grid((P.W + 15) / 16, (P.H + 15) / 16, P.nviews);
-    if (mode == 0) lookup_kernel<KMAX, DT, 0><<<grid, 256, 0, s>>>(P);
-    else lookup_kernel<KMAX, DT, 1><<<grid, 256, 0, s>>>(P);
+    if (mode == 0) lookup_kernel<KMAX, DT><<<grid, 256, 0, s>>>(P);
+    else lookup_adjoint_kernel<KMAX><<<grid, 256, 0, s>>>(P);
     return hipGetLastError();
 }
 
 template <int KMAX>
 static hipError_t launch_lookup_dt(const LookupParams& P, int mode, hipStream_t s) {
+    if (mode != 0) return launch_lookup_mode<KMAX, 0>(P, mode, s);  // the adjoint reads no texels
     switch (P.dtype) {
         case 0: return launch_lookup_mode<KMAX, 0>(P, mode, s);
         case 1: return launch_lookup_mode<KMAX, 1>(P, mode, s);
