@@ -316,7 +316,7 @@ __device__ __forceinline__ float neg_log1m(float u) { return -__logf(1.0f - u); 
 // ---------------------------------------------------------------------------
 struct GridWalk {
     float t, tx, ty, tz, dx, dy, dz;
-    int cx, cy, cz;
+    int ci;  // cell index in the padded grid (one border cell per side)
 
     __device__ __forceinline__ void init(const TraceParams& P, f3 x, f3 d, float t0) {
         const int G = P.grid_n;
@@ -338,9 +338,8 @@ struct GridWalk {
             }
         }
         t = t0;
-        cx = c[0];
-        cy = c[1];
-        cz = c[2];
+        const int Gp = G + 2;
+        ci = ((c[2] + 1) * Gp + (c[1] + 1)) * Gp + (c[0] + 1);
         tx = tm[0];
         ty = tm[1];
         tz = tm[2];
@@ -355,22 +354,24 @@ struct GridWalk {
     // both points need, not the sum of two maxima.  Points past the segment
     // come back as tend, with the majorant of their cell in sbA / sbB.  The
     // step is branch-free: the face crossed first is the one whose boundary
-    // equals the minimum, and cell indices are clamped to the grid, so a
-    // point that rounding carries past the last cell stays in it.  Every step
-    // raises the smallest boundary by one cell width along its axis, so the
-    // loop reaches tend within 3 (grid_n * segment length / cell width + 2)
-    // steps.
+    // equals the minimum, and the cell index moves by that axis's stride.
+    // The grid in LDS carries a border of cells that repeat the edge cells,
+    // so a step that rounding carries one cell past the grid reads the edge
+    // cell's majorant; the segment ends at the box, within rounding of the
+    // last face, so no walk goes two cells past it (the index is clamped to
+    // the padded grid all the same).  Every step raises the smallest
+    // boundary by one cell width along its axis, so the loop reaches tend
+    // within 3 (grid_n * segment length / cell width + 2) steps.
     __device__ __forceinline__ void next2(const TraceParams& P, const float* mg, f3 d, bool wantA, float tauA,
                                           float tauB, float tend, float& tA, float& sbA, float& tB, float& sbB,
                                           uint32_t& steps) {
-        const int G = P.grid_n, Gm = P.grid_n - 1;
-        const int sx = d.x > 0.0f ? 1 : -1, sy = d.y > 0.0f ? 1 : -1, sz = d.z > 0.0f ? 1 : -1;
+        const int Gp = P.grid_n + 2, Gp2 = Gp * Gp, last = Gp2 * Gp - 1;
         int phase = wantA ? 0 : 1;  // 0: looking for A, 1: looking for B, 2: done
         float tau = wantA ? tauA : tauB;
         tA = t;
         tB = tend;
         for (;;) {
-            const float s = mg[(cz * G + cy) * G + cx];
+            const float s = mg[ci];
             const float tmin = fminf(fminf(tx, ty), tz);
             const float te = fminf(tmin, tend);
             const float room = s * fmaxf(te - t, 0.0f);
@@ -394,9 +395,9 @@ struct GridWalk {
                     t = te;
                     ++steps;
                     const bool bx = tx == tmin, by = !bx && ty == tmin, bz = !bx && !by;
-                    cx = min(max(cx + (bx ? sx : 0), 0), Gm);
-                    cy = min(max(cy + (by ? sy : 0), 0), Gm);
-                    cz = min(max(cz + (bz ? sz : 0), 0), Gm);
+                    const int st = bx ? 1 : (by ? Gp : Gp2);
+                    const bool up = bx ? d.x > 0.0f : (by ? d.y > 0.0f : d.z > 0.0f);
+                    ci = min(max(up ? ci + st : ci - st, 0), last);
                     tx += bx ? dx : 0.0f;
                     ty += by ? dy : 0.0f;
                     tz += bz ? dz : 0.0f;

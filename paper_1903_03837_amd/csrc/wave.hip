@@ -55,12 +55,18 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     float* glds = (float*)(smem + P.lut_n);  // kGrad: dLUT [lut_n][4], dscale
     // cell majorants after the tables above
     float* mg = (float*)smem + 4 * P.lut_n * (MODE == kFrozen ? 2 : 1) + (MODE == kGrad ? 4 * P.lut_n + 1 : 0);
-    const int ncell = P.grid_n * P.grid_n * P.grid_n;
+    const int ncell = (P.grid_n + 2) * (P.grid_n + 2) * (P.grid_n + 2);  // padded grid
     for (int e = threadIdx.x; e < P.lut_n; e += blockDim.x) {
         lut_e[e] = ((const float4*)P.lut_e)[e];
         if constexpr (MODE == kFrozen) lut_s[e] = ((const float4*)P.lut_s)[e];
     }
-    for (int e = threadIdx.x; e < ncell; e += blockDim.x) mg[e] = P.maj[e];
+    // the cell majorants with a border that repeats the edge cells
+    for (int e = threadIdx.x; e < ncell; e += blockDim.x) {
+        const int Gp = P.grid_n + 2, ex = e % Gp, ey = (e / Gp) % Gp, ez = e / (Gp * Gp);
+        const int G1 = P.grid_n - 1;
+        const int cx = min(max(ex - 1, 0), G1), cy = min(max(ey - 1, 0), G1), cz = min(max(ez - 1, 0), G1);
+        mg[e] = P.maj[(cz * P.grid_n + cy) * P.grid_n + cx];
+    }
     if constexpr (MODE == kGrad)
         for (int e = threadIdx.x; e < 4 * P.lut_n + 1; e += blockDim.x) glds[e] = 0.0f;
     __syncthreads();
@@ -598,7 +604,7 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
     const long long ntiles = P.views ? (long long)P.nviews * P.vtiles : ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
     if (ntiles <= 0) return hipSuccess;
-    const size_t ncell = (size_t)P.grid_n * P.grid_n * P.grid_n;
+    const size_t ncell = (size_t)(P.grid_n + 2) * (P.grid_n + 2) * (P.grid_n + 2);  // padded grid in LDS
     const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
                        (MODE == kGrad ? sizeof(float) * (4 * (size_t)P.lut_n + 1) : 0) + sizeof(float) * ncell;
     int dev = 0, cus = 0, per_cu = 0;
