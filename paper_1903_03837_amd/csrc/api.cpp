@@ -554,6 +554,9 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     T.d_lf = d_lf;
     T.d_lut = d_lut;
     T.d_scale = d_scale;
+    // sample ranges of at least 8 samples, up to 4 per ray: finer work items
+    // even out the waves' finishing times
+    T.adj_parts = std::max(1, std::min(4, params->spp / 8));
     T.stats = nullptr;
     char* w = (char*)ws;
     T.ray_count = (unsigned int*)(w + 64) + 8;

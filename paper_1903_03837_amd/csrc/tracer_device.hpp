@@ -81,6 +81,7 @@ struct TraceParams {
     void* out;
     int32_t dtype;
     unsigned long long* stats;
+    int32_t adj_parts;  // adjoint: work items per listed ray (sample ranges)
     // SF points of both sets (workspace tables filled by sf_point with
     // inv_n = 1/n in FP32, the values the kernel would compute)
     const float4* tab_o;

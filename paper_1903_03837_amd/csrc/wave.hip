@@ -76,7 +76,10 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     const int lane = threadIdx.x & 63;
     const int rows = P.row_end - P.row_begin;
     const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
-    const long long nlist = MODE == kGrad ? (long long)*P.ray_count : 0;
+    // adjoint: each listed ray is split into adj_parts work items (ranges of
+    // its samples), for load balance; the scores add up in any order
+    const int parts = MODE == kGrad ? P.adj_parts : 1;
+    const long long nlist = MODE == kGrad ? (long long)*P.ray_count * parts : 0;
     const long long ntiles = MODE == kGrad ? (nlist + 63) / 64
                              : P.views   ? (long long)P.nviews * P.vtiles
                                          : (long long)tiles_i * tiles_j;
@@ -96,6 +99,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     int mode = kIdle;
     uint32_t k = 0, blk = 0;
     int s = 0, b = 0;
+    int s_end = P.spp;  // adjoint: end of this work item's sample range
     f3 po = mk3(0, 0, 0), d0 = po, acc = po, x = po, dir = po, T = po, L = po, om = po, C = po;
     float W = 1.0f, t = 0.0f, tend = 0.0f, Tr = 1.0f, up0 = 0.0f, up1 = 0.0f;
     Counters cnt = {0, 0, 0, 0, 0};
@@ -138,9 +142,14 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
             }
             if (q >= 0) {
                 int i = -1, j = -1;
+                int s_first = 0;
                 if constexpr (MODE == kGrad) {
                     if (q < nlist) {
-                        const uint32_t kk = P.ray_list[q];
+                        const long long ray = q / parts;
+                        const int part = (int)(q - ray * parts);
+                        s_first = part * P.spp / parts;
+                        s_end = (part + 1) * P.spp / parts;
+                        const uint32_t kk = P.ray_list[ray];
                         i = (int)(kk / (uint32_t)P.N);
                         j = (int)(kk - (uint32_t)i * (uint32_t)P.N);
                         const float* a = P.d_lf + 3 * (uint64_t)kk;
@@ -187,7 +196,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         po = mk3(a.x, a.y, a.z);
                         d0 = normalize(mk3(c.x, c.y, c.z) - po);
                         acc = mk3(0.0f, 0.0f, 0.0f);
-                        s = 0;
+                        s = s_first;
                         b = 0;
                         blk = 0;
                         mode = kStart;
@@ -463,7 +472,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     o[2] = L.z;
                 }
             }
-            if (next && ++s == P.spp) {
+            if (next && ++s == (MODE == kGrad ? s_end : P.spp)) {
                 if constexpr (MODE != kGrad) {
                     const float fs = (float)P.spp;
                     store_texel(P.out, P.dtype, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
