@@ -5,7 +5,6 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -49,6 +48,24 @@ size_t brick_copy_bytes(const lf_volume* v) {
 // the directions, the cell majorants of the grid (when used), the point
 // tables of both SF sets, then the brick copy of the volume.
 long long stored_rows(const lf_gen_params* p) { return p->origin_rows > 0 ? p->origin_rows : p->M; }
+
+// Sample ranges per ray (log2) of the path tracer's work items: 4 ranges
+// from 32 samples, 2 from 16.  A forward with several ranges keeps each
+// range's sum (12 bytes) until a second kernel adds them, so it splits only
+// while M*N*spp <= 2^31 (larger runs have enough rays per wave for balance).
+int part_log2(const lf_gen_params* p, bool forward) {
+    if (forward && (unsigned long long)p->M * (unsigned long long)p->N * (unsigned long long)p->spp > (1ull << 31))
+        return 0;
+    return p->spp >= 32 ? 2 : (p->spp >= 16 ? 1 : 0);
+}
+
+size_t part_sums_bytes(const lf_gen_params* p) {
+    if (p->surface) return 0;
+    const int pl = part_log2(p, true);
+    if (pl == 0) return 0;
+    const long long re = p->row_end <= 0 ? stored_rows(p) : p->row_end;
+    return align256(12 * (size_t)(re - p->row_begin) * (size_t)p->N << pl);
+}
 
 // Cells per axis of the majorant grid in use (0: the global majorant).
 int grid_cells(const lf_gen_params* p) { return p->majorant > 0.0f ? 0 : p->majorant_grid; }
@@ -341,7 +358,8 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     if (!lf_out) return fail(LF_E_ARG, "lf_out is NULL");
     if (params->surface && sample && sample != eval)
         return fail(LF_E_UNSUPPORTED, "frozen sampling does not apply to the isosurface variant");
-    const size_t need = gen_order_bytes(params) + brick_copy_bytes(vol) + surface_range_bytes(params);
+    const size_t need =
+        gen_order_bytes(params) + brick_copy_bytes(vol) + surface_range_bytes(params) + part_sums_bytes(params);
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -366,7 +384,10 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
     if (e == hipSuccess) e = setup_tracking(T, vol, sm, params, w, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate (set-up)");
     const int mode = (sample && sample != eval) ? lp::kFrozen : lp::kFwd;
+    T.part_log2 = part_log2(params, true);
+    T.part_sums = (float*)(w + gen_order_bytes(params) + brick_copy_bytes(vol) + surface_range_bytes(params));
     e = lp::launch_generate_wave(T, vol->type, mode, s);
+    if (e == hipSuccess && T.part_log2 > 0) e = lp::launch_combine_parts(T, s);
     if (e != hipSuccess) return hip_fail(e, "lf_generate");
     return LF_OK;
 }
@@ -554,9 +575,7 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     T.d_lf = d_lf;
     T.d_lut = d_lut;
     T.d_scale = d_scale;
-    // sample ranges of at least 8 samples, up to 4 per ray: finer work items
-    // even out the waves' finishing times
-    T.adj_parts = std::max(1, std::min(4, params->spp / 8));
+    T.part_log2 = part_log2(params, false);
     T.stats = nullptr;
     char* w = (char*)ws;
     T.ray_count = (unsigned int*)(w + 64) + 8;

@@ -75,6 +75,7 @@ hipError_t launch_active_rays(const TraceParams& P, hipStream_t s);
 hipError_t launch_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s);
 hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s);
+hipError_t launch_combine_parts(const TraceParams& P, hipStream_t s);
 // Table of the n SF points sf_point(n, i, inv_n) as float4 (w = 0).
 hipError_t launch_sf_table(int n, float inv_n, float4* out, hipStream_t s);
 

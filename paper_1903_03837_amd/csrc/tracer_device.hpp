@@ -81,7 +81,8 @@ struct TraceParams {
     void* out;
     int32_t dtype;
     unsigned long long* stats;
-    int32_t adj_parts;  // adjoint: work items per listed ray (sample ranges)
+    int32_t part_log2;  // work items per ray = 2^part_log2 sample ranges
+    float* part_sums;   // forward with several ranges: [rows][N][ranges][3]
     // SF points of both sets (workspace tables filled by sf_point with
     // inv_n = 1/n in FP32, the values the kernel would compute)
     const float4* tab_o;

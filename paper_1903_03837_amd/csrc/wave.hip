@@ -76,13 +76,17 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     const int lane = threadIdx.x & 63;
     const int rows = P.row_end - P.row_begin;
     const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
-    // adjoint: each listed ray is split into adj_parts work items (ranges of
-    // its samples), for load balance; the scores add up in any order
-    const int parts = MODE == kGrad ? P.adj_parts : 1;
+    // Each ray is split into 2^plog work items, ranges of its samples, for
+    // load balance (the rays of the last tiles would otherwise hold the grid
+    // long after most waves are done).  Adjoint: the scores add up in any
+    // order.  Forward with more than one range: each item leaves its partial
+    // sum in part_sums, and a second kernel adds the ranges in order.
+    const int plog = (MODE != kGrad && P.views) ? 0 : P.part_log2;
+    const int parts = 1 << plog;
     const long long nlist = MODE == kGrad ? (long long)*P.ray_count * parts : 0;
     const long long ntiles = MODE == kGrad ? (nlist + 63) / 64
                              : P.views   ? (long long)P.nviews * P.vtiles
-                                         : (long long)tiles_i * tiles_j;
+                                         : (long long)tiles_i * tiles_j * parts;
     const int home = blockIdx.x % kParts;
     const float inv_spp = 1.0f / (float)P.spp;
     const f3 O = mk3(P.O[0], P.O[1], P.O[2]);
@@ -99,7 +103,8 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     int mode = kIdle;
     uint32_t k = 0, blk = 0;
     int s = 0, b = 0;
-    int s_end = P.spp;  // adjoint: end of this work item's sample range
+    int s_end = P.spp;  // end of this work item's sample range
+    int part = 0;       // its range index
     f3 po = mk3(0, 0, 0), d0 = po, acc = po, x = po, dir = po, T = po, L = po, om = po, C = po;
     float W = 1.0f, t = 0.0f, tend = 0.0f, Tr = 1.0f, up0 = 0.0f, up1 = 0.0f;
     Counters cnt = {0, 0, 0, 0, 0};
@@ -142,14 +147,14 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
             }
             if (q >= 0) {
                 int i = -1, j = -1;
+                // work item q: sample range q mod parts of ray slot q / parts
                 int s_first = 0;
                 if constexpr (MODE == kGrad) {
                     if (q < nlist) {
-                        const long long ray = q / parts;
-                        const int part = (int)(q - ray * parts);
+                        part = (int)(q & (parts - 1));
                         s_first = part * P.spp / parts;
                         s_end = (part + 1) * P.spp / parts;
-                        const uint32_t kk = P.ray_list[ray];
+                        const uint32_t kk = P.ray_list[q >> plog];
                         i = (int)(kk / (uint32_t)P.N);
                         j = (int)(kk - (uint32_t)i * (uint32_t)P.N);
                         const float* a = P.d_lf + 3 * (uint64_t)kk;
@@ -178,9 +183,13 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         mode = kStart;
                     }
                 } else {
+                    const long long slot = q >> plog;
+                    part = (int)(q & (parts - 1));
+                    s_first = part * P.spp / parts;
+                    s_end = (part + 1) * P.spp / parts;
                     int ti, tj;
-                    tile_coords(q >> 6, tiles_i, tiles_j, ti, tj);
-                    const int oi = ti * 8 + (int)((q >> 3) & 7), dj = tj * 8 + (int)(q & 7);
+                    tile_coords(slot >> 6, tiles_i, tiles_j, ti, tj);
+                    const int oi = ti * 8 + (int)((slot >> 3) & 7), dj = tj * 8 + (int)(slot & 7);
                     if (oi < rows && dj < P.N) {
                         i = P.perm_o[oi];
                         j = P.perm_d[dj];
@@ -189,8 +198,10 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                 if (i >= 0) {
                     k = (uint32_t)i * (uint32_t)P.N + (uint32_t)j;
                     if (P.M == P.N && i == j) {
-                        // no direction: texel 0 (never listed for the adjoint)
-                        if constexpr (MODE != kGrad) store_texel(P.out, P.dtype, k, mk3(0.0f, 0.0f, 0.0f));
+                        // no direction: texel 0 (never listed for the adjoint;
+                        // with several ranges the combining kernel writes it)
+                        if constexpr (MODE != kGrad)
+                            if (parts == 1) store_texel(P.out, P.dtype, k, mk3(0.0f, 0.0f, 0.0f));
                     } else {
                         const float4 a = P.tab_o[i], c = P.tab_d[j];
                         po = mk3(a.x, a.y, a.z);
@@ -201,14 +212,14 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         blk = 0;
                         mode = kStart;
                         // A ray that misses the volume box in every sample: all
-                        // samples but the last are added here (each is the
-                        // environment radiance), and the last one runs as usual.
-                        // (The adjoint's ray list leaves such rays out.)
+                        // samples of the range but the last are added here (each
+                        // is the environment radiance), and the last one runs as
+                        // usual.  (The adjoint's ray list leaves such rays out.)
                         if constexpr (MODE != kGrad) {
                             if (misses_box(P, O, bmin, bmax, po, d0)) {
-                                for (int s2 = 1; s2 < P.spp; ++s2) acc = acc + env;
-                                cnt.samples += (uint32_t)(P.spp - 1);
-                                s = P.spp - 1;
+                                for (int s2 = s_first + 1; s2 < s_end; ++s2) acc = acc + env;
+                                cnt.samples += (uint32_t)(s_end - 1 - s_first);
+                                s = s_end - 1;
                             }
                         }
                     }
@@ -472,10 +483,18 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     o[2] = L.z;
                 }
             }
-            if (next && ++s == (MODE == kGrad ? s_end : P.spp)) {
+            if (next && ++s == s_end) {
                 if constexpr (MODE != kGrad) {
-                    const float fs = (float)P.spp;
-                    store_texel(P.out, P.dtype, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
+                    if (parts == 1) {
+                        const float fs = (float)P.spp;
+                        store_texel(P.out, P.dtype, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
+                    } else {  // this range's sum, for the combining kernel
+                        const uint64_t kl = (uint64_t)k - (uint64_t)P.row_begin * (uint32_t)P.N;
+                        float* o = P.part_sums + 3 * (kl * parts + part);
+                        o[0] = acc.x;
+                        o[1] = acc.y;
+                        o[2] = acc.z;
+                    }
                 }
                 mode = kIdle;
             } else {
@@ -611,7 +630,8 @@ hipError_t launch_active_rays(const TraceParams& P, hipStream_t s) {
 template <int VT, int MODE, bool STATS>
 static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
-    const long long ntiles = P.views ? (long long)P.nviews * P.vtiles : ((rows + 7) / 8) * (long long)((P.N + 7) / 8);
+    const long long ntiles = P.views ? (long long)P.nviews * P.vtiles
+                                     : ((rows + 7) / 8) * (long long)((P.N + 7) / 8) << P.part_log2;
     if (ntiles <= 0) return hipSuccess;
     const size_t ncell = (size_t)(P.grid_n + 2) * (P.grid_n + 2) * (P.grid_n + 2);  // padded grid in LDS
     const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
@@ -637,6 +657,33 @@ static hipError_t launch_wave_mode(const TraceParams& P, int mode, hipStream_t s
     if (P.stats)
         return mode == kFrozen ? launch_wave_t<VT, kFrozen, true>(P, s) : launch_wave_t<VT, kFwd, true>(P, s);
     return mode == kFrozen ? launch_wave_t<VT, kFrozen, false>(P, s) : launch_wave_t<VT, kFwd, false>(P, s);
+}
+
+// Light-field texels from the sample ranges: the ranges' sums in range
+// order, divided by spp (texels i == j are 0).
+__global__ void combine_parts_kernel(TraceParams P) {
+    const long long kl = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int rows = P.row_end - P.row_begin;
+    if (kl >= (long long)rows * P.N) return;
+    const int parts = 1 << P.part_log2;
+    const uint32_t i = (uint32_t)P.row_begin + (uint32_t)(kl / P.N), j = (uint32_t)(kl % P.N);
+    const uint32_t k = i * (uint32_t)P.N + j;
+    f3 acc = mk3(0.0f, 0.0f, 0.0f);
+    if (!(P.M == P.N && i == j)) {
+        const float* p = P.part_sums + 3 * (uint64_t)kl * parts;
+        acc = mk3(p[0], p[1], p[2]);
+        for (int q = 1; q < parts; ++q) acc = acc + mk3(p[3 * q], p[3 * q + 1], p[3 * q + 2]);
+        const float fs = (float)P.spp;
+        acc = mk3(acc.x / fs, acc.y / fs, acc.z / fs);
+    }
+    store_texel(P.out, P.dtype, k, acc);
+}
+
+hipError_t launch_combine_parts(const TraceParams& P, hipStream_t s) {
+    const long long n = (long long)(P.row_end - P.row_begin) * P.N;
+    if (n <= 0) return hipSuccess;
+    combine_parts_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P);
+    return hipGetLastError();
 }
 
 hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipStream_t s) {

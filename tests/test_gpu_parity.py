@@ -558,6 +558,38 @@ def test_backward_from_stored_sample_radiance(lp, orc):
     assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a)
 
 
+@pytest.mark.parametrize("spp,ranges", [(8, 1), (16, 2), (32, 4)])
+def test_mean_over_sample_ranges(lp, spp, ranges):
+    """The texel is the FP32 sum of each range of spp / R consecutive
+    samples in order, then of the R range sums in order, divided by spp
+    (R = 4 from 32 samples, 2 from 16); the kept per-sample radiance shows
+    each sample's value."""
+    M = N = 64
+    sc = S.config(1, M=M, N=N, spp=spp)
+    vol, med, light, prm, _ = lp.device_scene(sc)
+    srad = torch.full((M, N, spp, 3), float("nan"), dtype=torch.float32, device="cuda")
+    lf = lp.generate(vol, med, light, prm, sample_radiance=srad)
+    torch.cuda.synchronize()
+    field = lf.reshape(-1, 3).cpu().numpy()
+    sr = srad.reshape(M * N, spp, 3).cpu().numpy()
+    whole = ~np.isnan(sr).any(axis=(1, 2))
+    assert whole.sum() > 0.3 * M * N
+    n = spp // ranges
+    total = np.zeros((M * N, 3), np.float32)
+    for r_ in range(ranges):
+        part = np.zeros((M * N, 3), np.float32)
+        for s_ in range(r_ * n, (r_ + 1) * n):
+            part = part + sr[:, s_]
+        total = part if r_ == 0 else total + part
+    assert np.array_equal((total / np.float32(spp))[whole], field[whole])
+    # the same field without keeping the samples, and split by rows
+    assert np.array_equal(lp.generate(vol, med, light, prm).reshape(-1, 3).cpu().numpy(), field)
+    half = dataclasses.replace(prm, row_begin=M // 2, row_end=M)
+    out = torch.zeros_like(lf)
+    lp.generate(vol, med, light, half, out=out)
+    assert np.array_equal(out.reshape(-1, 3).cpu().numpy()[M // 2 * N:], field[M // 2 * N:])
+
+
 def test_backward_matches_finite_differences(lp, orc):
     """Central differences (h = 1e-3) of the GPU forward in frozen sampling."""
     sc = grad_scene()
