@@ -184,9 +184,11 @@ int lf_points(int32_t n, float* xyz_out, const float* query, int64_t nq, int32_t
  * keyed by `seed`, counter (k, sample, bounce << 8 | purpose, block), so the
  * result is independent of launch shape and row split.  The mean is summed in
  * FP32 over R equal ranges of consecutive samples, each in sample order, then
- * the R range sums in order, then divided by spp: R = 4 when spp >= 32, 2
- * when spp >= 16, else 1, and R = 1 whenever M*N*spp > 2^31 (the ranges are
- * work items of their own; the workspace then holds their sums).
+ * the R range sums in order, then divided by spp.  R = min(R_spp, R_rays):
+ * R_spp = 4 when spp >= 32, 2 when spp >= 16, else 1; R_rays = 4 when
+ * M*N < 1572864, 2 when M*N < 12582912, else 1; and R = 1 whenever
+ * M*N*spp > 2^31 (the ranges are work items of their own, for load balance;
+ * the workspace then holds their sums).
  *   eval:   medium evaluated.   sample: NULL, or the medium that decides
  *   collisions (frozen sampling: the path is importance-weighted from sample
  *   to eval; used for finite-difference checks of the adjoint).
