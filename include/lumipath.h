@@ -217,6 +217,16 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
               int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out, void* ws,
               size_t* ws_bytes, void* stream);
 
+/* Lookup, loss gradient and adjoint in one pass (Sec. 2 lookup and its
+ * transpose, for an L2 image loss): img receives the views of lf exactly as
+ * lf_lookup's forward mode writes them, and d_lf (float32
+ * [origin_rows][N][3]) is incremented by the transpose applied to
+ * img - target, the gradient of 1/2 |img - target|^2 (atomics).  target:
+ * float32 [n_views][H][W][3], read only.  Other arguments as for lf_lookup. */
+int lf_lookup_l2(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
+                 int32_t W, int32_t H, int32_t K, const float* target, float* img, float* d_lf, void* ws,
+                 size_t* ws_bytes, void* stream);
+
 /* Ground-truth views: the path tracer of lf_generate along pinhole camera
  * rays, the reference the paper compares its light-field views with (Sec. 4
  * evaluation).  For each pixel (x, y) of each of the n_views cameras (host

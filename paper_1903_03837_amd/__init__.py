@@ -96,12 +96,14 @@ def library():
         L.lf_generate_backward.argtypes = [P, P, P, P, P, P, P, P, C.POINTER(C.c_size_t), P]
         L.lf_lookup.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 P, P, P, P, C.POINTER(C.c_size_t), P]
+        L.lf_lookup_l2.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, P,
+                                   C.POINTER(C.c_size_t), P]
         L.lf_majorant_grid.argtypes = [P, P, P, P, P]
         L.lf_render_views.argtypes = [P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P,
                                       C.POINTER(C.c_size_t), P]
         L.lf_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.POINTER(C.c_size_t), P]
-        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_majorant_grid,
-                  L.lf_render_views, L.lf_ssim):
+        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_lookup_l2,
+                  L.lf_majorant_grid, L.lf_render_views, L.lf_ssim):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -415,6 +417,28 @@ def lookup_adjoint(dimg: torch.Tensor, prm: GenParams, cams: Sequence[Camera], K
     ws, sz = _workspace(library().lf_lookup, *args)
     _check(library().lf_lookup(*args, _ptr(ws), C.byref(sz), _stream()))
     return d_lf
+
+
+def lookup_l2(lf: torch.Tensor, prm: GenParams, cams: Sequence[Camera], target: torch.Tensor, K: int = 5,
+              img: Optional[torch.Tensor] = None, d_lf: Optional[torch.Tensor] = None):
+    """lf_lookup_l2: (img [V, H, W, 3], d_lf [rows, N, 3]); img = lookup(lf),
+    d_lf += lookup transpose of (img - target)."""
+    dt = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}[lf.dtype]
+    target = target.contiguous().float()
+    V, H, W, _ = target.shape
+    _need(lf, prm.rows * prm.N * 3, lf.dtype, "lf")
+    if img is None:
+        img = torch.empty_like(target)
+    _need(img, V * H * W * 3, torch.float32, "img")
+    if d_lf is None:
+        d_lf = torch.zeros((prm.rows, prm.N, 3), dtype=torch.float32, device=lf.device)
+    _need(d_lf, prm.rows * prm.N * 3, torch.float32, "d_lf")
+    p = prm.c()
+    cs = _cams(cams)
+    args = [_ptr(lf), dt, C.byref(p), cs, V, W, H, K, _ptr(target), _ptr(img), _ptr(d_lf)]
+    ws, sz = _workspace(library().lf_lookup_l2, *args)
+    _check(library().lf_lookup_l2(*args, _ptr(ws), C.byref(sz), _stream()))
+    return img, d_lf
 
 
 # ----------------------------------------------------------------- autograd

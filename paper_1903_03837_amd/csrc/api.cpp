@@ -599,10 +599,11 @@ int lf_generate_backward(const lf_volume* vol, const lf_medium* medium, const lf
     return LF_OK;
 }
 
-int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
-              int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out, void* ws,
-              size_t* ws_bytes, void* stream) {
-    g_err.clear();
+// lf_lookup and lf_lookup_l2: mode 0 forward, 1 adjoint, 2 fused L2 (views,
+// their loss gradient against `target`, and its adjoint).
+static int run_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams,
+                      int32_t n_views, int32_t W, int32_t H, int32_t K, int32_t mode, float* img, const float* target,
+                      float* d_lf, int32_t* nn_out, void* ws, size_t* ws_bytes, void* stream) {
     int r;
     if ((r = check_params(params, false))) return r;
     if (!cams) return fail(LF_E_ARG, "cams is NULL");
@@ -610,11 +611,11 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
     if ((long long)W * H > (1ll << 30) || (long long)n_views * W * H > (1ll << 40))
         return fail(LF_E_RANGE, "image too large");
     if (K < 1 || K > 9) return fail(LF_E_ARG, "K must be in [1, 9] (got %d)", K);
-    if (mode != LF_LOOKUP_FORWARD && mode != LF_LOOKUP_ADJOINT) return fail(LF_E_ARG, "unknown mode %d", mode);
     if (dtype < LF_F32 || dtype > LF_BF16) return fail(LF_E_ARG, "unknown light-field dtype %d", dtype);
     if (!img) return fail(LF_E_ARG, "img is NULL");
-    if (mode == LF_LOOKUP_FORWARD && !lf) return fail(LF_E_ARG, "lf is NULL");
-    if (mode == LF_LOOKUP_ADJOINT && !d_lf) return fail(LF_E_ARG, "d_lf is NULL");
+    if (mode != LF_LOOKUP_ADJOINT && !lf) return fail(LF_E_ARG, "lf is NULL");
+    if (mode != LF_LOOKUP_FORWARD && !d_lf) return fail(LF_E_ARG, "d_lf is NULL");
+    if (mode == 2 && !target) return fail(LF_E_ARG, "target is NULL");
     // workspace: the point tables of both SF sets
     const size_t tab_o_bytes = align256(16 * (size_t)params->M);
     const size_t need = tab_o_bytes + align256(16 * (size_t)params->N);
@@ -643,7 +644,8 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
     L.lf = lf;
     L.img = img;
     L.d_lf = d_lf;
-    L.nn = nn_out;
+    L.target = target;
+    L.nn = mode == LF_LOOKUP_FORWARD ? nn_out : nullptr;
     L.tab_o = (const float4*)ws;
     L.tab_d = (const float4*)((char*)ws + tab_o_bytes);
     // per-view geometry in double, rounded once to float
@@ -700,6 +702,22 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
         if (e != hipSuccess) return hip_fail(e, "lf_lookup");
     }
     return LF_OK;
+}
+
+int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
+              int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out, void* ws,
+              size_t* ws_bytes, void* stream) {
+    g_err.clear();
+    if (mode != LF_LOOKUP_FORWARD && mode != LF_LOOKUP_ADJOINT) return fail(LF_E_ARG, "unknown mode %d", mode);
+    return run_lookup(lf, dtype, params, cams, n_views, W, H, K, mode, img, nullptr, d_lf, nn_out, ws, ws_bytes,
+                      stream);
+}
+
+int lf_lookup_l2(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
+                 int32_t W, int32_t H, int32_t K, const float* target, float* img, float* d_lf, void* ws,
+                 size_t* ws_bytes, void* stream) {
+    g_err.clear();
+    return run_lookup(lf, dtype, params, cams, n_views, W, H, K, 2, img, target, d_lf, nullptr, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -29,6 +29,7 @@ struct LookupParams {
     const void* lf;
     float* img;
     float* d_lf;
+    const float* target;    // fused L2 adjoint: target views
     int32_t* nn;
     const float4* tab_o;    // SF point tables (workspace), float4 per point
     const float4* tab_d;

@@ -101,7 +101,10 @@ __device__ __forceinline__ void wave_scatter_add(float* d_lf, bool pending, uint
 }
 
 // Adjoint of one pixel: d_lf[a][b] += w_ab * dimg for its K x K pairs.
-template <int KMAX>
+// L2: the pixel's view value is formed first, exactly as the forward lookup
+// forms it, and written to img; dimg = value - target (the gradient of
+// 1/2 |img - target|^2).  Otherwise dimg is read from img.
+template <int KMAX, int DT, bool L2>
 __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int px, int py, int v) {
     bool live = px < P.W && py < P.H;
     int ia[KMAX], jb[KMAX];
@@ -138,12 +141,19 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
                 sf_nearest(P.N, P.invN, SfTable{P.tab_d}, qd, sf_zone(P.N, qd.z), C);
                 select_k<KMAX>(C, P.K, jb, db);
             }
-            const float* g = P.img + 3 * pix;
-            gi = mk3(g[0], g[1], g[2]);
+            if constexpr (!L2) {
+                const float* g = P.img + 3 * pix;
+                gi = mk3(g[0], g[1], g[2]);
+            }
             if constexpr (KMAX == 1) {
                 wa[0] = ia[0] < P.orows ? 1.0f : 0.0f;
                 wb[0] = 1.0f;
                 inv = 1.0f;
+                if constexpr (L2) {
+                    const bool covered = ia[0] < P.orows;
+                    const uint64_t t = (uint64_t)(covered ? ia[0] : 0) * (uint64_t)P.N + (uint64_t)jb[0];
+                    gi = covered ? load_texel<DT>(P.lf, t) : mk3(0.0f, 0.0f, 0.0f);
+                }
             } else {
                 float wsum = 0.0f;
 #pragma unroll
@@ -157,11 +167,40 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
                     for (int c = 0; c < KMAX; ++c)
                         wsum += (P.degenerate && ia[a] == jb[c]) ? 0.0f : wa[a] * wb[c];
                 inv = wsum > 0.0f ? 1.0f / wsum : 0.0f;
+                if constexpr (L2) {
+                    // the forward's blend, term for term in the same order
+                    f3 acc = mk3(0.0f, 0.0f, 0.0f);
+                    if (wsum > 0.0f) {
+#pragma unroll
+                        for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+                            for (int c = 0; c < KMAX; ++c) {
+                                const bool bad = P.degenerate && ia[a] == jb[c];
+                                const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
+                                const int ai = (ia[a] >= 0 && ia[a] < P.orows) ? ia[a] : 0;
+                                const uint64_t t = (uint64_t)ai * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
+                                acc = fma3(load_texel<DT>(P.lf, t), w, acc);
+                            }
+                    }
+                    gi = acc;
+                }
                 sort_by_index<KMAX>(ia, wa);
                 sort_by_index<KMAX>(jb, wb);
             }
+            if constexpr (L2) {
+                float* o = P.img + 3 * pix;
+                o[0] = gi.x;
+                o[1] = gi.y;
+                o[2] = gi.z;
+                const float* tg = P.target + 3 * pix;
+                gi = gi - mk3(tg[0], tg[1], tg[2]);
+            }
         } else {
             live = false;
+            if constexpr (L2) {
+                float* o = P.img + 3 * pix;
+                o[0] = o[1] = o[2] = 0.0f;
+            }
         }
     }
 #pragma unroll
@@ -177,15 +216,15 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
         }
 }
 
-// Adjoint: every lane of the wave takes part in the aggregated scatter (no
-// early exit).  8 waves per SIMD (64 VGPRs, a few values spilled) ran 3 %
+// Adjoint (and the fused L2 variant): every lane of the wave takes part in
+// the aggregated scatter (no early exit).  8 waves per SIMD (64 VGPRs, a few values spilled) ran 3 %
 // faster than 7 waves with no spills.
-template <int KMAX>
+template <int KMAX, int DT, bool L2>
 __global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
-    lookup_adjoint_pixel<KMAX>(P, px, py, blockIdx.z);
+    lookup_adjoint_pixel<KMAX, DT, L2>(P, px, py, blockIdx.z);
 }
 
 template <int KMAX, int DT>
@@ -294,13 +333,14 @@ template <int KMAX, int DT>
 static hipError_t launch_lookup_mode(const LookupParams& P, int mode, hipStream_t s) {
     dim3 grid((P.W + 15) / 16, (P.H + 15) / 16, P.nviews);
     if (mode == 0) lookup_kernel<KMAX, DT><<<grid, 256, 0, s>>>(P);
-    else lookup_adjoint_kernel<KMAX><<<grid, 256, 0, s>>>(P);
+    else if (mode == 1) lookup_adjoint_kernel<KMAX, 0, false><<<grid, 256, 0, s>>>(P);
+    else lookup_adjoint_kernel<KMAX, DT, true><<<grid, 256, 0, s>>>(P);
     return hipGetLastError();
 }
 
 template <int KMAX>
 static hipError_t launch_lookup_dt(const LookupParams& P, int mode, hipStream_t s) {
-    if (mode != 0) return launch_lookup_mode<KMAX, 0>(P, mode, s);  // the adjoint reads no texels
+    if (mode == 1) return launch_lookup_mode<KMAX, 0>(P, mode, s);  // the plain adjoint reads no texels
     switch (P.dtype) {
         case 0: return launch_lookup_mode<KMAX, 0>(P, mode, s);
         case 1: return launch_lookup_mode<KMAX, 1>(P, mode, s);

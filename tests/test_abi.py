@@ -223,6 +223,19 @@ def test_lookup_workspace_query(lp):
     assert r == LF_E_WORKSPACE
 
 
+def test_lookup_l2_rejects(lp):
+    _, _, _, prm = scene(lp)
+    ok = lp.Camera((5, 0, 0), (0, 0, 0), (0, 0, 1), 0.5)
+    arr = lp._cams([ok])
+    sz = C.c_size_t(1 << 20)
+    L = lp.library()
+    assert L.lf_lookup_l2(FAKE, 0, C.byref(prm), arr, 1, 8, 8, 5, None, FAKE, FAKE, FAKE, C.byref(sz), None) == LF_E_ARG
+    assert "target" in err(lp)
+    assert L.lf_lookup_l2(None, 0, C.byref(prm), arr, 1, 8, 8, 5, FAKE, FAKE, FAKE, FAKE, C.byref(sz), None) == LF_E_ARG
+    assert L.lf_lookup_l2(FAKE, 0, C.byref(prm), arr, 1, 8, 8, 5, FAKE, FAKE, None, FAKE, C.byref(sz), None) == LF_E_ARG
+    assert L.lf_lookup_l2(FAKE, 5, C.byref(prm), arr, 1, 8, 8, 5, FAKE, FAKE, FAKE, FAKE, C.byref(sz), None) == LF_E_ARG
+
+
 def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     import paper_1903_03837_amd as lp
     monkeypatch.setattr(lp, "_lib", None)

@@ -500,6 +500,27 @@ def test_lookup_adjoint_stored_rows(lp, orc, K):
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("K,dtype", [(5, "f32"), (1, "f32"), (5, "f16"), (9, "bf16")])
+def test_lookup_l2_fused(lp, K, dtype):
+    """lf_lookup_l2 writes the forward views bit for bit and adds the
+    transpose of (views - target) to d_lf, as lookup, subtraction and
+    lookup_adjoint do separately (to float-atomic rounding)."""
+    M = N = 256
+    V, W, H = 3, 96, 64
+    sc = S.config(1, M=M, N=N, views=V, width=W, height=H)
+    vol, med, light, prm, cams = lp.device_scene(sc)
+    lf = lp.generate(vol, med, light, prm, dtype=dtype)
+    torch.manual_seed(0)
+    target = torch.rand((V, H, W, 3), device="cuda")
+    img_ref = lp.lookup(lf, prm, cams, W, H, K)
+    d_ref = lp.lookup_adjoint(img_ref - target, prm, cams, K)
+    img, d_lf = lp.lookup_l2(lf, prm, cams, target, K)
+    torch.cuda.synchronize()
+    assert torch.equal(img, img_ref)
+    a, b = d_lf.double(), d_ref.double()
+    assert float((a - b).norm()) <= 1e-5 * float(b.norm())
+
+
 # ------------------------------------------------------------------ adjoint
 def grad_scene():
     sc = S.config(1, M=48, N=48, spp=6, max_bounces=3, g=0.3)
