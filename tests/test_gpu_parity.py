@@ -500,14 +500,18 @@ def test_lookup_adjoint_stored_rows(lp, orc, K):
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("K,dtype", [(5, "f32"), (1, "f32"), (5, "f16"), (9, "bf16")])
-def test_lookup_l2_fused(lp, K, dtype):
+@pytest.mark.parametrize("K,dtype,rows", [(5, "f32", 0), (1, "f32", 0), (5, "f16", 0), (9, "bf16", 0),
+                                          (5, "f32", 128), (1, "f32", 128)])
+def test_lookup_l2_fused(lp, K, dtype, rows):
     """lf_lookup_l2 writes the forward views bit for bit and adds the
     transpose of (views - target) to d_lf, as lookup, subtraction and
-    lookup_adjoint do separately (to float-atomic rounding)."""
+    lookup_adjoint do separately (to float-atomic rounding); also with only
+    the upper-hemisphere origin rows stored."""
     M = N = 256
     V, W, H = 3, 96, 64
-    sc = S.config(1, M=M, N=N, views=V, width=W, height=H)
+    sc = S.config(1, M=M, N=N, views=V, width=W, height=H, origin_rows=rows)
+    if rows:
+        sc = sc.replace(cams=S.seam_cameras(math.sqrt(3.0))[:V])
     vol, med, light, prm, cams = lp.device_scene(sc)
     lf = lp.generate(vol, med, light, prm, dtype=dtype)
     torch.manual_seed(0)
