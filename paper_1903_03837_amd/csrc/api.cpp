@@ -66,6 +66,14 @@ int part_log2(const lf_gen_params* p, bool forward) {
     return by_spp < by_rays ? by_spp : by_rays;
 }
 
+// The same rule for ground-truth views, by pixels instead of rays.
+int view_part_log2(int spp, unsigned long long pixels) {
+    if (pixels * (unsigned long long)spp > (1ull << 31)) return 0;
+    const int by_spp = spp >= 32 ? 2 : (spp >= 16 ? 1 : 0);
+    const int by_px = pixels < 8ull * 196608 ? 2 : (pixels < 64ull * 196608 ? 1 : 0);
+    return by_spp < by_px ? by_spp : by_px;
+}
+
 size_t part_sums_bytes(const lf_gen_params* p) {
     if (p->surface) return 0;
     const int pl = part_log2(p, true);
@@ -461,7 +469,11 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
     p1.row_end = 1;
     p1.jitter = 0;
     const size_t views_bytes = align256(sizeof(lp::ViewCam) * (size_t)n_views);
-    const size_t need = gen_order_bytes(&p1) + views_bytes + brick_copy_bytes(vol) + surface_range_bytes(&p1);
+    const unsigned long long pixels = (unsigned long long)n_views * (unsigned long long)W * (unsigned long long)H;
+    const int vpl = p1.surface ? 0 : view_part_log2(p1.spp, pixels);
+    const size_t psum_bytes = vpl ? align256((size_t)(12 * pixels) << vpl) : 0;
+    const size_t need =
+        gen_order_bytes(&p1) + views_bytes + brick_copy_bytes(vol) + surface_range_bytes(&p1) + psum_bytes;
     r = check_workspace(ws, ws_bytes, need);
     if (r == 1) {
         *ws_bytes = need;
@@ -500,7 +512,10 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
                             (float*)(w + gen_order_bytes(&p1) + views_bytes + brick_copy_bytes(vol)), s);
     } else {
         if (e == hipSuccess) e = setup_tracking(T, vol, medium, &p1, w, s);
+        T.part_log2 = vpl;
+        T.part_sums = (float*)(w + gen_order_bytes(&p1) + views_bytes + brick_copy_bytes(vol) + surface_range_bytes(&p1));
         if (e == hipSuccess) e = lp::launch_generate_wave(T, vol->type, lp::kFwd, s);
+        if (e == hipSuccess && vpl > 0) e = lp::launch_combine_parts(T, s);
     }
     if (e != hipSuccess) return hip_fail(e, "lf_render_views");
     return LF_OK;

@@ -46,8 +46,10 @@
 namespace lp {
 
 // STATS: the work counters of `stats` are kept (a separate instantiation, so
-// the plain kernel spends no registers on them).
-template <int VT, int MODE, bool STATS>
+// the plain kernel spends no registers on them).  VIEWS: ground-truth views
+// (pinhole rays of pixel tiles) instead of light-field rays, also a separate
+// instantiation so that the light-field kernel carries none of its code.
+template <int VT, int MODE, bool STATS, bool VIEWS>
 __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     extern __shared__ float4 smem[];
     float4* lut_e = smem;
@@ -81,11 +83,11 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     // long after most waves are done).  Adjoint: the scores add up in any
     // order.  Forward with more than one range: each item leaves its partial
     // sum in part_sums, and a second kernel adds the ranges in order.
-    const int plog = (MODE != kGrad && P.views) ? 0 : P.part_log2;
+    const int plog = P.part_log2;
     const int parts = 1 << plog;
     const long long nlist = MODE == kGrad ? (long long)*P.ray_count * parts : 0;
     const long long ntiles = MODE == kGrad ? (nlist + 63) / 64
-                             : P.views   ? (long long)P.nviews * P.vtiles
+                             : VIEWS     ? (long long)P.nviews * P.vtiles * parts
                                          : (long long)tiles_i * tiles_j * parts;
     const int home = blockIdx.x % kParts;
     const float inv_spp = 1.0f / (float)P.spp;
@@ -161,12 +163,16 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         adj = mk3(a[0] * inv_spp, a[1] * inv_spp, a[2] * inv_spp);
                         pass = P.srad ? 1 : 0;
                     }
-                } else if (P.views) {
+                } else if constexpr (VIEWS) {
                     // pixel of an 8 x 8 tile of a view: the ray from the eye through its centre
-                    const uint32_t t = (uint32_t)(q >> 6);
+                    const long long slot = q >> plog;
+                    part = (int)(q & (parts - 1));
+                    s_first = part * P.spp / parts;
+                    s_end = (part + 1) * P.spp / parts;
+                    const uint32_t t = (uint32_t)(slot >> 6);
                     const uint32_t v = t / (uint32_t)P.vtiles, rem = t - v * (uint32_t)P.vtiles;
                     const uint32_t ty = rem / (uint32_t)P.vtx, tx = rem - ty * (uint32_t)P.vtx;
-                    const int py = (int)ty * 8 + (int)((q >> 3) & 7), px = (int)tx * 8 + (int)(q & 7);
+                    const int py = (int)ty * 8 + (int)((slot >> 3) & 7), px = (int)tx * 8 + (int)(slot & 7);
                     if (py < P.H && px < P.W) {
                         const ViewCam& cam = P.views[v];
                         const float ndx = (2.0f * ((float)px + 0.5f) / (float)P.W - 1.0f) * cam.sx;
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                                        mk3(cam.right[0], cam.right[1], cam.right[2]) * ndx +
                                        mk3(cam.up[0], cam.up[1], cam.up[2]) * ndy);
                         acc = mk3(0.0f, 0.0f, 0.0f);
-                        s = 0;
+                        s = s_first;
                         b = 0;
                         blk = 0;
                         mode = kStart;
@@ -283,9 +289,9 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     }
                 }
                 // light-field ray: origin on S (jittered); view ray: the eye
-                base = P.views ? po : O + po * P.R;
+                base = VIEWS ? po : O + po * P.R;
                 n = po;
-                A = (P.jitter && !P.views) ? P.jit_rad * sqrtf(u01(r.x)) : 0.0f;
+                A = (P.jitter && !VIEWS) ? P.jit_rad * sqrtf(u01(r.x)) : 0.0f;
                 ua = u01(r.y);
                 T = mk3(1.0f, 1.0f, 1.0f);
                 W = 1.0f;
@@ -476,7 +482,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                 }
             } else {
                 acc = acc + L;
-                if (P.srad && !P.views) {
+                if (P.srad && !VIEWS) {
                     float* o = P.srad + 3 * ((uint64_t)k * (uint32_t)P.spp + (uint32_t)s);
                     o[0] = L.x;
                     o[1] = L.y;
@@ -627,11 +633,11 @@ hipError_t launch_active_rays(const TraceParams& P, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int VT, int MODE, bool STATS>
+template <int VT, int MODE, bool STATS, bool VIEWS>
 static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
-    const long long ntiles = P.views ? (long long)P.nviews * P.vtiles
-                                     : ((rows + 7) / 8) * (long long)((P.N + 7) / 8) << P.part_log2;
+    const long long ntiles = (P.views ? (long long)P.nviews * P.vtiles : ((rows + 7) / 8) * (long long)((P.N + 7) / 8))
+                             << P.part_log2;
     if (ntiles <= 0) return hipSuccess;
     const size_t ncell = (size_t)(P.grid_n + 2) * (P.grid_n + 2) * (P.grid_n + 2);  // padded grid in LDS
     const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
@@ -640,36 +646,43 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE, STATS>, 256, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE, STATS, VIEWS>, 256, lds);
     if (e != hipSuccess) return e;
     long long blocks = (long long)cus * (per_cu > 0 ? per_cu : 1);
     // at least one tile per wave (list lengths are only known on the device;
     // waves that find no chunk exit at once)
     const long long need = (ntiles + 3) / 4;
     if (blocks > need) blocks = need;
-    gen_wave_kernel<VT, MODE, STATS><<<(unsigned)blocks, 256, lds, s>>>(P);
+    gen_wave_kernel<VT, MODE, STATS, VIEWS><<<(unsigned)blocks, 256, lds, s>>>(P);
     return hipGetLastError();
 }
 
 template <int VT>
 static hipError_t launch_wave_mode(const TraceParams& P, int mode, hipStream_t s) {
-    if (mode == kGrad) return launch_wave_t<VT, kGrad, false>(P, s);
+    if (P.views) return launch_wave_t<VT, kFwd, false, true>(P, s);  // ground-truth views: plain forward
+    if (mode == kGrad) return launch_wave_t<VT, kGrad, false, false>(P, s);
     if (P.stats)
-        return mode == kFrozen ? launch_wave_t<VT, kFrozen, true>(P, s) : launch_wave_t<VT, kFwd, true>(P, s);
-    return mode == kFrozen ? launch_wave_t<VT, kFrozen, false>(P, s) : launch_wave_t<VT, kFwd, false>(P, s);
+        return mode == kFrozen ? launch_wave_t<VT, kFrozen, true, false>(P, s)
+                               : launch_wave_t<VT, kFwd, true, false>(P, s);
+    return mode == kFrozen ? launch_wave_t<VT, kFrozen, false, false>(P, s)
+                           : launch_wave_t<VT, kFwd, false, false>(P, s);
 }
 
 // Light-field texels from the sample ranges: the ranges' sums in range
 // order, divided by spp (texels i == j are 0).
-__global__ void combine_parts_kernel(TraceParams P) {
+__global__ void combine_parts_kernel(TraceParams P, long long n) {
     const long long kl = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int rows = P.row_end - P.row_begin;
-    if (kl >= (long long)rows * P.N) return;
+    if (kl >= n) return;
     const int parts = 1 << P.part_log2;
-    const uint32_t i = (uint32_t)P.row_begin + (uint32_t)(kl / P.N), j = (uint32_t)(kl % P.N);
-    const uint32_t k = i * (uint32_t)P.N + j;
+    bool none = false;  // texel i == j of the light field
+    uint32_t k = (uint32_t)kl;  // views: the pixel
+    if (!P.views) {
+        const uint32_t i = (uint32_t)P.row_begin + (uint32_t)(kl / P.N), j = (uint32_t)(kl % P.N);
+        k = i * (uint32_t)P.N + j;
+        none = P.M == P.N && i == j;
+    }
     f3 acc = mk3(0.0f, 0.0f, 0.0f);
-    if (!(P.M == P.N && i == j)) {
+    if (!none) {
         const float* p = P.part_sums + 3 * (uint64_t)kl * parts;
         acc = mk3(p[0], p[1], p[2]);
         for (int q = 1; q < parts; ++q) acc = acc + mk3(p[3 * q], p[3 * q + 1], p[3 * q + 2]);
@@ -680,9 +693,9 @@ __global__ void combine_parts_kernel(TraceParams P) {
 }
 
 hipError_t launch_combine_parts(const TraceParams& P, hipStream_t s) {
-    const long long n = (long long)(P.row_end - P.row_begin) * P.N;
+    const long long n = P.views ? (long long)P.nviews * P.H * P.W : (long long)(P.row_end - P.row_begin) * P.N;
     if (n <= 0) return hipSuccess;
-    combine_parts_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P);
+    combine_parts_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, n);
     return hipGetLastError();
 }
 
