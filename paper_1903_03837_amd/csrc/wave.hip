@@ -154,8 +154,8 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                 if constexpr (MODE == kGrad) {
                     if (q < nlist) {
                         part = (int)(q & (parts - 1));
-                        s_first = part * P.spp / parts;
-                        s_end = (part + 1) * P.spp / parts;
+                        s_first = (part * P.spp) >> plog;
+                        s_end = ((part + 1) * P.spp) >> plog;
                         const uint32_t kk = P.ray_list[q >> plog];
                         i = (int)(kk / (uint32_t)P.N);
                         j = (int)(kk - (uint32_t)i * (uint32_t)P.N);
@@ -167,8 +167,8 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     // pixel of an 8 x 8 tile of a view: the ray from the eye through its centre
                     const long long slot = q >> plog;
                     part = (int)(q & (parts - 1));
-                    s_first = part * P.spp / parts;
-                    s_end = (part + 1) * P.spp / parts;
+                    s_first = (part * P.spp) >> plog;
+                    s_end = ((part + 1) * P.spp) >> plog;
                     const uint32_t t = (uint32_t)(slot >> 6);
                     const uint32_t v = t / (uint32_t)P.vtiles, rem = t - v * (uint32_t)P.vtiles;
                     const uint32_t ty = rem / (uint32_t)P.vtx, tx = rem - ty * (uint32_t)P.vtx;
@@ -191,8 +191,8 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                 } else {
                     const long long slot = q >> plog;
                     part = (int)(q & (parts - 1));
-                    s_first = part * P.spp / parts;
-                    s_end = (part + 1) * P.spp / parts;
+                    s_first = (part * P.spp) >> plog;
+                    s_end = ((part + 1) * P.spp) >> plog;
                     int ti, tj;
                     tile_coords(slot >> 6, tiles_i, tiles_j, ti, tj);
                     const int oi = ti * 8 + (int)((slot >> 3) & 7), dj = tj * 8 + (int)(slot & 7);
