@@ -100,12 +100,151 @@ __device__ __forceinline__ void wave_scatter_add(float* d_lf, bool pending, uint
     }
 }
 
+// Per-wave LDS of the MFMA scatter: the weight rows of the wave's 64 pixels
+// over its dictionaries of distinct origin and direction texel indices.
+constexpr int kDict = 8;
+struct ScatterLds {
+    float u[64 * kDict];  // [pixel][origin entry]: w_a / sum of pair weights
+    float v[64 * kDict];  // [pixel][direction entry]: w_b
+    float g[64 * 3];      // [pixel][channel]: the pixel's adjoint dimg
+    int dict[2 * kDict];  // origin indices, then direction indices
+};
+
+// Builds the wave's dictionary of the distinct values among the flagged
+// entries val[s] of all lanes, and each entry's position in it (-1 for an
+// unflagged entry).  The loop is wave-uniform: each pass takes the value of
+// the first lane with a pending entry in slot s and retires every entry
+// equal to it.  Returns the dictionary size, or -1 if it would exceed kDict.
+template <int KMAX>
+__device__ __forceinline__ int wave_dictionary(const int (&val)[KMAX], bool (&pend)[KMAX], int (&pos)[KMAX],
+                                               int* dict) {
+    int n = 0;
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) pos[s] = -1;
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+        uint64_t m = __ballot(pend[s]);
+        while (m) {
+            if (n == kDict) return -1;
+            const int leader = __ffsll((long long)m) - 1;
+            const int x = __builtin_amdgcn_readlane(val[s], leader);
+            // slots before s hold no pending entry, and no value twice in a lane
+#pragma unroll
+            for (int t = s; t < KMAX; ++t) {
+                const bool hit = pend[t] && val[t] == x;
+                pos[t] = hit ? n : pos[t];
+                pend[t] = pend[t] && !hit;
+            }
+            if ((threadIdx.x & 63) == 0) dict[n] = x;
+            ++n;
+            m = __ballot(pend[s]);
+        }
+    }
+    return n;
+}
+
+// Wave-level LDS ordering: every lane's writes before, every lane's reads after.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The adjoint scatter of a wave as a dense contraction over its 64 pixels:
+// with dictionaries A (origin indices) and B (direction indices) of the
+// wave's texels, d_lf[A_x][B_y][ch] += sum_p u_p[x] v_p[y] g_p[ch], where
+// u_p / v_p hold pixel p's normalised origin / direction weights at its own
+// entries and 0 elsewhere.  A pair (a, b) that no pixel holds gets exactly
+// 0, and a degenerate pair (a == b, same SF set) only ever collects
+// excluded pairs, so both are skipped, as the per-pair scatter skips them.
+// Two v_mfma_f32_16x16x4_f32 chains over the pixels, 4 per instruction:
+// rows are u (rows 8..15 repeat 0..7); the first chain's columns are v * g0
+// (0..7) and v * g1 (8..15), the second's v * g2, so rows 0..7 of the first
+// hold channels 0 and 1 and the top-left block of the second channel 2 (one
+// product per instruction cannot hold all three: a fourth block of scaled
+// rows times scaled columns would need a quotient of channels).
+// Returns false (nothing written to d_lf) when a
+// dictionary would exceed kDict entries or an adjoint value is not finite
+// (a zero weight times an infinite one would spread NaN over other texels).
+template <int KMAX>
+__device__ __forceinline__ bool mfma_scatter(const LookupParams& P, ScatterLds& L, bool live, const int (&ia)[KMAX],
+                                             const float (&wa)[KMAX], const int (&jb)[KMAX],
+                                             const float (&wb)[KMAX], float inv, f3 gi) {
+    const int lane = threadIdx.x & 63;
+    const bool finite = isfinite(gi.x) && isfinite(gi.y) && isfinite(gi.z);
+    if (__ballot(!finite)) return false;
+    float u[KMAX];
+    bool pa[KMAX], pb[KMAX];
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+        u[a] = wa[a] * inv;
+        pa[a] = live && ia[a] >= 0 && ia[a] < P.orows && u[a] != 0.0f;
+        pb[a] = live && jb[a] >= 0 && wb[a] != 0.0f;
+    }
+    int xa[KMAX], xb[KMAX];
+    const int na = wave_dictionary<KMAX>(ia, pa, xa, L.dict);
+    if (na < 0) return false;
+    const int nb = wave_dictionary<KMAX>(jb, pb, xb, L.dict + kDict);
+    if (nb < 0) return false;
+    if (na == 0 || nb == 0) return true;  // no weighted pair in the wave
+
+    float* ur = L.u + lane * kDict;
+    float* vr = L.v + lane * kDict;
+    *(float4*)ur = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    *(float4*)(ur + 4) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    *(float4*)vr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    *(float4*)(vr + 4) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+        if (xa[a] >= 0) ur[xa[a]] = u[a];
+        if (xb[a] >= 0) vr[xb[a]] = wb[a];
+    }
+    L.g[3 * lane + 0] = gi.x;
+    L.g[3 * lane + 1] = gi.y;
+    L.g[3 * lane + 2] = gi.z;
+    wave_lds_sync();
+
+    // A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k (k: pixel 4 kb + k)
+    const int col = lane & 7, kq = lane >> 4;
+    const bool hi = (lane & 15) >= kDict;
+    const int g01 = hi ? 1 : 0;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f c01 = {0.0f, 0.0f, 0.0f, 0.0f}, c2 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb) {
+        const int p = 4 * kb + kq;
+        const float uu = L.u[p * kDict + col];
+        const float vv = L.v[p * kDict + col];
+        c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(uu, vv * L.g[3 * p + g01], c01, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(uu, vv * L.g[3 * p + 2], c2, 0, 0, 0);
+    }
+
+    // D[i][j] in lane j + 16 (i / 4), register i % 4; rows 0..7 are in lanes 0..31
+    if (kq < 2) {
+        const int j = lane & 15, y = j & 7;
+        const int db = L.dict[kDict + y];
+        const uint64_t col_off = (uint64_t)db;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = 4 * kq + r;
+            const int da = L.dict[x];
+            bool pair = x < na && y < nb;
+            if (KMAX > 1 && P.degenerate && da == db) pair = false;
+            float* t = P.d_lf + 3 * ((uint64_t)da * (uint64_t)P.N + col_off);
+            if (pair && c01[r] != 0.0f) atomicAdd(t + (j < kDict ? 0 : 1), c01[r]);
+            if (pair && j < kDict && c2[r] != 0.0f) atomicAdd(t + 2, c2[r]);
+        }
+    }
+    wave_lds_sync();  // the rows and dictionaries are rewritten by the next call
+    return true;
+}
+
 // Adjoint of one pixel: d_lf[a][b] += w_ab * dimg for its K x K pairs.
 // L2: the pixel's view value is formed first, exactly as the forward lookup
 // forms it, and written to img; dimg = value - target (the gradient of
 // 1/2 |img - target|^2).  Otherwise dimg is read from img.
 template <int KMAX, int DT, bool L2>
-__device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int px, int py, int v) {
+__device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, ScatterLds& L, int px, int py, int v) {
     bool live = px < P.W && py < P.H;
     int ia[KMAX], jb[KMAX];
     float wa[KMAX], wb[KMAX];
@@ -203,6 +342,9 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
             }
         }
     }
+    // K = 9 lists alone fill a dictionary: only the per-pair path below
+    if constexpr (KMAX < kDict)
+        if (mfma_scatter<KMAX>(P, L, live, ia, wa, jb, wb, inv, gi)) return;
 #pragma unroll
     for (int a = 0; a < KMAX; ++a)
 #pragma unroll
@@ -222,9 +364,10 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, int 
 template <int KMAX, int DT, bool L2>
 __global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ ScatterLds lds[4];
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
-    lookup_adjoint_pixel<KMAX, DT, L2>(P, px, py, blockIdx.z);
+    lookup_adjoint_pixel<KMAX, DT, L2>(P, lds[wave], px, py, blockIdx.z);
 }
 
 template <int KMAX, int DT>

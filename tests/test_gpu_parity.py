@@ -421,6 +421,70 @@ def test_lookup_adjoint(lp, orc, M, N, K):
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
+def tile_rays_disc(cam, W, H, R):
+    """disc / R^2 of the sphere test for the centre pixel of every 8x8 tile
+    (the lookup's pinhole camera, FP64): [H // 8, W // 8]."""
+    eye, tgt, up = (np.asarray(x, np.float64) for x in (cam.eye, cam.target, cam.up))
+    f = (tgt - eye) / np.linalg.norm(tgt - eye)
+    rt = np.cross(f, up)
+    rt /= np.linalg.norm(rt)
+    u = np.cross(rt, f)
+    th = math.tan(0.5 * cam.vfov)
+    ty, tx = np.meshgrid(np.arange(H // 8), np.arange(W // 8), indexing="ij")
+    ndx = (2.0 * (tx * 8 + 4.0) / W - 1.0) * th * W / H
+    ndy = (1.0 - 2.0 * (ty * 8 + 4.0) / H) * th
+    d = f + rt * ndx[..., None] + u * ndy[..., None]
+    d /= np.linalg.norm(d, axis=-1)[..., None]
+    b = d @ eye
+    return (b * b - (eye @ eye - R * R)) / (R * R)
+
+
+@pytest.mark.parametrize("c,M,W,H,K", [(5, 1024, 512, 512, 5), (2, 2048, 1920, 1080, 5),
+                                       (2, 2048, 1920, 1080, 1), (2, 2048, 1920, 1080, 9)])
+def test_lookup_adjoint_full_resolution(lp, orc, c, M, W, H, K):
+    """At the workloads' view sizes the 64 pixels of a wave share a handful of
+    neighbours, and the scatter runs as a dense contraction per wave (MFMA)
+    over the wave's distinct origin and direction texels; waves with more
+    distinct texels (K = 9 always) take the per-pair path.  The adjoint
+    image is nonzero on 240 random 8x8 tiles and on up to 60 tiles next to
+    the silhouette, where front and back hits meet the same SF point and
+    degenerate pairs occur; the oracle transposes those pixels only (the
+    other pixels still enter the waves' neighbour dictionaries)."""
+    sc = S.config(c, M=M, N=M, views=1, width=W, height=H)
+    R = sc.params.radius
+    prm = lp.GenParams(M=M, N=M, radius=R)
+    cams = [lp.Camera(x.eye, x.target, x.up, x.vfov) for x in sc.cams]
+    rng = np.random.default_rng(11)
+    mask = np.zeros((H, W), bool)
+    for tx, ty in zip(rng.integers(0, W // 8, 240), rng.integers(0, H // 8, 240)):
+        mask[8 * ty:8 * ty + 8, 8 * tx:8 * tx + 8] = True
+    disc = tile_rays_disc(sc.cams[0], W, H, R)
+    edge = np.argwhere((disc > 0.0) & (disc < 0.02))
+    for ty, tx in edge[rng.permutation(len(edge))[:60]]:
+        mask[8 * ty:8 * ty + 8, 8 * tx:8 * tx + 8] = True
+    pix = orc.all_pixels(1, W, H)
+    sel = pix[mask.reshape(-1)[pix[:, 2].astype(np.int64) * W + pix[:, 1]]]
+    # pixels inside an FP32 decision band of the neighbour search (either
+    # neighbour set may differ from FP64) keep a zero adjoint
+    _, _, mg = orc.lookup(np.zeros((M, M, 3), np.float32), sc.params, sc.cams, W, H, K, sel)
+    clear = (mg[:, 0] > 1e-4) & (mg[:, 1] > BAND) & (mg[:, 2] > 1e-3) & ((mg[:, 3] > BAND) | (K == 1))
+    assert clear.mean() > 0.97
+    keep = sel[clear]
+    vals = rng.standard_normal((len(keep), 3)).astype(np.float32)
+    dimg = np.zeros((1, H, W, 3), np.float32)
+    dimg[0, keep[:, 2], keep[:, 1]] = vals
+    d_lf = lp.lookup_adjoint(torch.from_numpy(dimg).cuda(), prm, cams, K)
+    torch.cuda.synchronize()
+    ref = orc.lookup_adjoint(sc.params, sc.cams, W, H, K, keep, vals.astype(np.float64))
+    got = d_lf.reshape(-1).cpu().numpy().astype(np.float64)
+    assert np.count_nonzero(ref) > 1000
+    # the lookup's bar: FP32 view rays move each tent weight by ~1e-6 / r
+    r = math.sqrt(4 * math.pi / M)
+    assert np.linalg.norm(got - ref) <= LOOKUP_C / r * np.linalg.norm(ref)
+    # texels no selected pixel reaches stay exactly zero
+    assert np.all(got[ref == 0.0] == 0.0)
+
+
 # ------------------------------------------------- upper-hemisphere origins
 def test_generate_stored_rows(lp, orc):
     """origin_rows = M/2 writes the first half of the full field, bit for bit,
