@@ -538,24 +538,33 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
 
 // Spatial order of count consecutive SF indices base..base+count-1 of a set
 // of n points: bands of B indices, each sorted by azimuth (rank counting).
-__global__ void sf_order_kernel(int base, int count, int band, int32_t* out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
-    const int lo = (e / band) * band;
-    const int hi = min(count, lo + band);
-    const float fe = sf_frac(base + e);
-    int rank = 0;
-    for (int f = lo; f < hi; ++f) {
-        const float ff = sf_frac(base + f);
-        rank += ff < fe || (ff == fe && f < e);
+// One workgroup per band, its azimuths staged in LDS (B <= 1272 for
+// n <= 65535).
+constexpr int kMaxBand = 1280;
+__global__ __launch_bounds__(256) void sf_order_kernel(int base, int count, int band, int32_t* out) {
+    __shared__ float fr[kMaxBand];
+    const int lo = blockIdx.x * band;
+    const int cnt = min(count - lo, band);
+    for (int t = (int)threadIdx.x; t < cnt; t += 256) fr[t] = sf_frac(base + lo + t);
+    __syncthreads();
+    for (int t = (int)threadIdx.x; t < cnt; t += 256) {
+        const float fe = fr[t];
+        int rank = 0;
+        for (int f = 0; f < cnt; ++f) {
+            const float ff = fr[f];
+            rank += ff < fe || (ff == fe && f < t);
+        }
+        out[lo + rank] = base + lo + t;
     }
-    out[lo + rank] = base + e;
 }
 
 // Compacts the rays (in the spatial tile order) whose adjoint is nonzero and
 // which can reach the volume box (a ray that misses it in every sample has no
 // collision and so no score).
-__global__ void active_rays_kernel(TraceParams P) {
+// One atomic per workgroup and trip claims the list slots of its four waves
+// (one per wave made the single counter the bottleneck).
+__global__ __launch_bounds__(256) void active_rays_kernel(TraceParams P) {
+    __shared__ unsigned wave_n[4], wave_at[4];
     const int rows = P.row_end - P.row_begin;
     const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
     const long long total = (long long)tiles_i * tiles_j * 64;
@@ -585,10 +594,21 @@ __global__ void active_rays_kernel(TraceParams P) {
             }
         }
         const uint64_t m = __ballot(take);
-        unsigned at = 0;
-        if (lane == 0 && m) at = atomicAdd(P.ray_count, (unsigned)__popcll(m));
-        at = __shfl(at, 0, 64);
-        if (take) P.ray_list[at + __popcll(m & lt_mask)] = k;
+        const int wave = threadIdx.x >> 6;
+        if (lane == 0) wave_n[wave] = (unsigned)__popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned n0 = wave_n[0], n1 = wave_n[1], n2 = wave_n[2], n3 = wave_n[3];
+            const unsigned tot = n0 + n1 + n2 + n3;
+            const unsigned at = tot ? atomicAdd(P.ray_count, tot) : 0u;
+            wave_at[0] = at;
+            wave_at[1] = at + n0;
+            wave_at[2] = at + n0 + n1;
+            wave_at[3] = at + n0 + n1 + n2;
+        }
+        __syncthreads();
+        if (take) P.ray_list[wave_at[wave] + __popcll(m & lt_mask)] = k;
+        __syncthreads();  // wave_n / wave_at are rewritten by the next trip
     }
 }
 
@@ -618,8 +638,9 @@ hipError_t launch_wave_setup(const TraceParams& P, const float* sample_lut, int 
                              hipStream_t s) {
     wave_setup_kernel<<<1, 256, 0, s>>>(sample_lut, lut_n, sample_scale, given, sigbar, ctr);
     const int rows = P.row_end - P.row_begin;
-    if (rows > 0) sf_order_kernel<<<(rows + 255) / 256, 256, 0, s>>>(P.row_begin, rows, band_size(P.M), perm_o);
-    sf_order_kernel<<<(P.N + 255) / 256, 256, 0, s>>>(0, P.N, band_size(P.N), perm_d);
+    const int bo = band_size(P.M), bd = band_size(P.N);
+    if (rows > 0) sf_order_kernel<<<(rows + bo - 1) / bo, 256, 0, s>>>(P.row_begin, rows, bo, perm_o);
+    sf_order_kernel<<<(P.N + bd - 1) / bd, 256, 0, s>>>(0, P.N, bd, perm_d);
     return hipGetLastError();
 }
 
