@@ -210,11 +210,22 @@ __device__ __forceinline__ int sf_nearest(int n, float inv_n, const Pts& pts, f3
     return c;
 }
 
+// Comparators (a, b), a < b, that leave the five smallest of nine keys in
+// positions 0..4 in order: Batcher's odd-even merge sort of 16 inputs
+// restricted to 9, then pruned of every comparator the first five outputs do
+// not need.  By the 0-1 principle it suffices that this holds for all 512
+// inputs of zeros and ones, which a host test checks.
+constexpr int kSel5of9 = 23;
+__device__ constexpr int kSel5of9Net[kSel5of9][2] = {
+    {0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5},
+    {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {0, 8}, {4, 8}, {2, 4}, {1, 2}, {3, 4}};
+
 // Keep the K nearest candidates in (distance^2, index) order.  A squared
 // distance is a non-negative float, so its bits order like the value: each
 // candidate becomes one 64-bit key (d2 bits, index), and keys compare in
-// (distance, index) order with one unsigned comparison.  Nine rounds of
-// odd-even transposition sort the nine keys (registers only).
+// (distance, index) order with one unsigned comparison.  Up to five kept:
+// the selection network above (23 compare-exchanges); nine: nine rounds of
+// odd-even transposition (36).  Registers only.
 template <int KMAX>
 __device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, float* out_d2) {
     uint64_t key[9];
@@ -223,6 +234,15 @@ __device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, flo
     if constexpr (KMAX == 1) {
 #pragma unroll
         for (int a = 1; a < 9; ++a) key[0] = key[a] < key[0] ? key[a] : key[0];
+    } else if constexpr (KMAX <= 5) {
+#pragma unroll
+        for (int c = 0; c < kSel5of9; ++c) {
+            const int a = kSel5of9Net[c][0], b = kSel5of9Net[c][1];
+            const uint64_t lo = key[a] < key[b] ? key[a] : key[b];
+            const uint64_t hi = key[a] < key[b] ? key[b] : key[a];
+            key[a] = lo;
+            key[b] = hi;
+        }
     } else {
 #pragma unroll
         for (int p = 0; p < 9; ++p)
