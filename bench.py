@@ -389,6 +389,7 @@ def main():
     for kk in (1, K):
         v_img = lp.lookup(lf, prm, qcams, qw, qh, kk)
         quality[f"ssim_K{kk}"] = float(lp.ssim(v_img, gt, data_range=gmax).mean())
+        quality[f"cw_ssim_K{kk}"] = float(lp.cw_ssim(v_img, gt, data_range=gmax).mean())
         quality[f"rel_l1_K{kk}"] = float((v_img - gt).abs().sum() / gt.abs().sum())
     log("bench: light-field views vs ground truth " + json.dumps(quality))
 

@@ -164,7 +164,7 @@ const char* lf_last_error(void);
 int lf_version(void);
 
 /* Spherical-Fibonacci point set and its inverse query (Sec. 2, SF point
- * equation; nearest-neighbour query with "up to nine neighbors" and the
+ * equation; nearest-neighbour query over at most nine neighbours and the
  * filter kernel of size R sqrt(4 pi / N)).
  *   xyz_out: NULL or float [n][3], p_i for i < n (frac(i/Phi) in FP64).
  *   query:   NULL or float [nq][3] unit vectors; then idx_out int32 [nq][K]
@@ -228,7 +228,7 @@ int lf_lookup_l2(const void* lf, int32_t dtype, const lf_gen_params* params, con
                  size_t* ws_bytes, void* stream);
 
 /* Ground-truth views: the path tracer of lf_generate along pinhole camera
- * rays, the reference the paper compares its light-field views with (Sec. 4
+ * rays, the reference the paper compares its light-field views with (Sec. 3
  * evaluation).  For each pixel (x, y) of each of the n_views cameras (host
  * array, consumed before return; pixel centres, row 0 at the top, as in
  * lf_lookup) img[((v * H + y) * W + x) * 3 + c] (device float32) receives
@@ -254,6 +254,28 @@ int lf_render_views(const lf_volume* vol, const lf_medium* medium, const lf_ligh
  * size query with ws == NULL. */
 int lf_ssim(const float* a, const float* b, int32_t n_images, int32_t W, int32_t H, float data_range, double* out,
             void* ws, size_t* ws_bytes, void* stream);
+
+/* Mean CW-SSIM (complex-wavelet SSIM, Wang & Simoncelli 2005, Sampat et
+ * al. 2009; the second index the paper reports in its image-quality
+ * evaluation, Sec. 3) of n_images pairs of RGB float32 images a, b
+ * (device, [n_images][H][W][3]).  The paper names only a steerable pyramid
+ * of eight levels in total; here: eight complex subbands (2 scales x 4
+ * orientations) of a filter bank defined on the DFT grid of the image, with
+ * signed frequency f = u (2u < n) or u - n, w = 2 pi f / n, r = |w|,
+ * theta = atan2(w_y, w_x): radial window cos(pi/2 log2(r / r_s)) for
+ * |log2(r / r_s)| < 1, r_s = pi / 2^(s+1), s = 0, 1; one-sided angular
+ * window cos(d)^3 for |d| < pi/2, d = theta - pi k / 4 wrapped to
+ * (-pi, pi], k = 0..3.  For each channel and subband the local index
+ * (2 |sum c_a conj(c_b)| + K) / (sum |c_a|^2 + sum |c_b|^2 + K) over every
+ * 7 x 7 window inside the image, K = 49 (0.01 data_range)^2 (data_range 0:
+ * K = 0, and a window with 0 / 0 counts as 1), averaged over positions,
+ * subbands and channels.  out: device float64 [n_images].  7 <= W, H <=
+ * 4096; data_range >= 0.  A direct DFT (O(W H (W + H)) per plane) in FP32
+ * with FP64 sums of the local terms in a fixed order: the result is the same
+ * on every run.  Workspace: size query with ws == NULL (about 150 W H
+ * bytes).  Stream-ordered on `stream`. */
+int lf_cw_ssim(const float* a, const float* b, int32_t n_images, int32_t W, int32_t H, float data_range,
+               double* out, void* ws, size_t* ws_bytes, void* stream);
 
 /* Cell majorants of the majorant grid that lf_generate and
  * lf_generate_backward track against (piecewise-constant majorant; the grid

@@ -105,7 +105,7 @@ int32_t orc_zone(int64_t n, double qz, double* margin) {
     return k;
 }
 
-/* K-neighbour query (Sec. 2: "up to nine neighbors", five of them used per
+/* K-neighbour query (Sec. 2: at most nine neighbours, five of them used per
  * hit point, weighted by distance with a filter of size R sqrt(4 pi / N)).
  * The nine are the nearest point and its eight Fibonacci-lattice
  * neighbours i* +- {F(k-1), F(k), F(k+1), F(k+2)}. */

@@ -102,8 +102,9 @@ def library():
         L.lf_render_views.argtypes = [P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P,
                                       C.POINTER(C.c_size_t), P]
         L.lf_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.POINTER(C.c_size_t), P]
+        L.lf_cw_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.POINTER(C.c_size_t), P]
         for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_lookup_l2,
-                  L.lf_majorant_grid, L.lf_render_views, L.lf_ssim):
+                  L.lf_majorant_grid, L.lf_render_views, L.lf_ssim, L.lf_cw_ssim):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -354,6 +355,21 @@ def ssim(a: torch.Tensor, b: torch.Tensor, data_range: float = 1.0) -> torch.Ten
     args = [_ptr(a), _ptr(b), n, W, H, float(data_range), _ptr(out)]
     ws, sz = _workspace(L.lf_ssim, *args)
     _check(L.lf_ssim(*args, _ptr(ws), C.byref(sz), _stream()))
+    return out
+
+
+def cw_ssim(a: torch.Tensor, b: torch.Tensor, data_range: float = 1.0) -> torch.Tensor:
+    """lf_cw_ssim: mean CW-SSIM [n] (float64) of image pairs [n, H, W, 3] (float32)."""
+    if a.shape != b.shape or a.dim() != 4 or a.shape[-1] != 3:
+        raise ValueError("a and b must both be [n, H, W, 3]")
+    a = a.contiguous().float()
+    b = b.contiguous().float()
+    n, H, W, _ = a.shape
+    out = torch.empty(n, dtype=torch.float64, device=a.device)
+    L = library()
+    args = [_ptr(a), _ptr(b), n, W, H, float(data_range), _ptr(out)]
+    ws, sz = _workspace(L.lf_cw_ssim, *args)
+    _check(L.lf_cw_ssim(*args, _ptr(ws), C.byref(sz), _stream()))
     return out
 
 

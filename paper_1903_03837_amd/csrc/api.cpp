@@ -561,6 +561,42 @@ int lf_ssim(const float* a, const float* b, int32_t n_images, int32_t W, int32_t
     return LF_OK;
 }
 
+int lf_cw_ssim(const float* a, const float* b, int32_t n_images, int32_t W, int32_t H, float data_range,
+               double* out, void* ws, size_t* ws_bytes, void* stream) {
+    g_err.clear();
+    if (!a || !b || !out) return fail(LF_E_ARG, "a, b and out must be non-NULL");
+    if (n_images < 1) return fail(LF_E_ARG, "n_images must be >= 1");
+    if (W < 7 || H < 7) return fail(LF_E_ARG, "images must be at least 7 x 7 (the window)");
+    if (W > 4096 || H > 4096) return fail(LF_E_RANGE, "W and H must be <= 4096");
+    if (!(data_range >= 0.0f) || !std::isfinite(data_range)) return fail(LF_E_ARG, "data_range must be >= 0");
+    const size_t plane = align256(sizeof(float2) * (size_t)W * (size_t)H * 6);
+    const size_t tw_w = align256(sizeof(float2) * (size_t)W), tw_h = align256(sizeof(float2) * (size_t)H);
+    const size_t need = tw_w + tw_h + 3 * plane + align256(sizeof(double) * lp::cw_ssim_slots(W, H));
+    int r = check_workspace(ws, ws_bytes, need);
+    if (r == 1) {
+        *ws_bytes = need;
+        return LF_OK;
+    }
+    if (r) return r;
+    char* w = (char*)ws;
+    lp::CwParams P;
+    P.a = a;
+    P.b = b;
+    P.W = W;
+    P.H = H;
+    P.K = (float)(49.0 * (0.01 * data_range) * (0.01 * data_range));
+    P.tw_w = (float2*)w;
+    P.tw_h = (float2*)(w + tw_w);
+    P.spec = (float2*)(w + tw_w + tw_h);
+    P.t1 = (float2*)(w + tw_w + tw_h + plane);
+    P.t2 = (float2*)(w + tw_w + tw_h + 2 * plane);
+    P.slots = (double*)(w + tw_w + tw_h + 3 * plane);
+    P.out = out;
+    hipError_t e = lp::launch_cw_ssim(P, n_images, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lf_cw_ssim");
+    return LF_OK;
+}
+
 int lf_majorant_grid(const lf_volume* vol, const lf_medium* sample, const lf_gen_params* params, float* out,
                      void* stream) {
     g_err.clear();

@@ -50,6 +50,23 @@ struct SsimParams {
 hipError_t launch_ssim(const SsimParams& P, int n_images, hipStream_t s);
 size_t ssim_partial_count(int n_images, int W, int H);
 
+// CW-SSIM of image pairs (metrics.hip): workspace pieces and launch.
+struct CwParams {
+    const float* a;
+    const float* b;
+    int32_t W, H;
+    float K;           // 49 (0.01 data_range)^2
+    float2* tw_w;      // [W] twiddles (cos, sin) of 2 pi m / W
+    float2* tw_h;      // [H]
+    float2* spec;      // [6][H][W] spectra of the six planes of one image pair
+    float2* t1;        // [6][H][W] scratch planes
+    float2* t2;        // [6][H][W]
+    double* slots;     // workgroup sums of one image pair
+    double* out;       // [n_images]
+};
+size_t cw_ssim_slots(int W, int H);
+hipError_t launch_cw_ssim(const CwParams& P, int n_images, hipStream_t s);
+
 hipError_t launch_points(int n, float* xyz, const float* query, long long nq, int K, int* idx, float* w,
                          hipStream_t s);
 // Halo bricks along an axis of n >= 2 voxels: base voxels 0 .. n-2, three per brick.

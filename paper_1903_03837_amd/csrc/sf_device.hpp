@@ -1,6 +1,6 @@
 // sf_device.hpp -- device building blocks shared by the light-field kernels:
 // small vector algebra, Philox4x32-10, the spherical-Fibonacci point set and
-// its O(1) inverse (nearest point and "up to nine" neighbours).
+// its O(1) inverse (nearest point and at most nine neighbours).
 //
 // Spherical Fibonacci set (Fink et al. 2019, Sec. 2, SF point equation):
 //   p_i = (cos phi_i sin theta_i, sin phi_i sin theta_i, z_i),

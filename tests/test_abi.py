@@ -242,3 +242,32 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(lp, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         lp.library()
+
+
+def test_cw_ssim_workspace_and_rejects(lp):
+    """lf_cw_ssim: workspace size query (no GPU call) and host-side rejects."""
+    L = lp.library()
+    a, b, out = C.c_void_p(0x10000), C.c_void_p(0x20000), C.c_void_p(0x30000)
+
+    def query(W, H, rng=1.0, n=1, pa=a):
+        sz = C.c_size_t(0)
+        rc = L.lf_cw_ssim(pa, b, n, W, H, rng, out, None, C.byref(sz), None)
+        return rc, sz.value
+
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    for W, H in ((7, 7), (480, 270), (512, 512), (4096, 9)):
+        rc, sz = query(W, H)
+        assert rc == 0, lp.last_error() if hasattr(lp, "last_error") else rc
+        gx, gy = (W - 6 + 15) // 16, (H - 6 + 15) // 16
+        want = a256(8 * W) + a256(8 * H) + 3 * a256(48 * W * H) + a256(8 * gx * gy * 3 * 8)
+        assert sz == want, (W, H, sz, want)
+    assert query(6, 100)[0] == -1          # below the 7 x 7 window
+    assert query(100, 6)[0] == -1
+    assert query(4097, 100)[0] == -2       # DFT size limit
+    assert query(100, 100, rng=-1.0)[0] == -1
+    assert query(100, 100, rng=float("inf"))[0] == -1
+    assert query(100, 100, n=0)[0] == -1
+    assert query(100, 100, pa=None)[0] == -1
+    assert query(100, 100, rng=0.0)[0] == 0  # K = 0 is allowed
