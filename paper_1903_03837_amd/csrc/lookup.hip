@@ -7,10 +7,13 @@
 // view ray -> front/back hits on S (tangential rays discarded) -> O(1)
 // inverse SF mapping of each hit -> K nearest of the nine lattice
 // candidates -> tent weights -> K x K gathers (25 at K = 5) -> normalised
-// blend.  The adjoint mode sorts each pixel's neighbour lists by index, so
-// the pixels of a wave, which share their neighbour sets, hold the same
-// texel in the same pair slot; equal texels are summed across the wave and
-// one float atomic per channel is issued per distinct texel.
+// blend.  The adjoint sums each wave's contributions before its atomics:
+// as a dense contraction over the wave's 64 pixels on MFMA when the wave's
+// distinct origin and direction neighbours fit dictionaries of 8 (most
+// waves at view resolution), otherwise per pair slot after sorting each
+// pixel's neighbour lists by index (neighbouring pixels then hold equal
+// texels in equal slots, which are summed across the wave with DPP).  One
+// float atomic per channel is issued per distinct texel either way.
 #include <hip/hip_fp16.h>
 
 #include "internal.hpp"

@@ -439,17 +439,11 @@ def tile_rays_disc(cam, W, H, R):
     return (b * b - (eye @ eye - R * R)) / (R * R)
 
 
-@pytest.mark.parametrize("c,M,W,H,K", [(5, 1024, 512, 512, 5), (2, 2048, 1920, 1080, 5),
-                                       (2, 2048, 1920, 1080, 1), (2, 2048, 1920, 1080, 9)])
-def test_lookup_adjoint_full_resolution(lp, orc, c, M, W, H, K):
-    """At the workloads' view sizes the 64 pixels of a wave share a handful of
-    neighbours, and the scatter runs as a dense contraction per wave (MFMA)
-    over the wave's distinct origin and direction texels; waves with more
-    distinct texels (K = 9 always) take the per-pair path.  The adjoint
-    image is nonzero on 240 random 8x8 tiles and on up to 60 tiles next to
-    the silhouette, where front and back hits meet the same SF point and
-    degenerate pairs occur; the oracle transposes those pixels only (the
-    other pixels still enter the waves' neighbour dictionaries)."""
+def full_resolution_adjoint(lp, orc, c, M, W, H, K, n_inf=0):
+    """d_lf from the GPU and the oracle for one view of workload c at full
+    resolution: the adjoint image is nonzero on the decided pixels of 240
+    random 8x8 tiles and of up to 60 tiles next to the silhouette; n_inf of
+    those pixels carry +inf in channel 0."""
     sc = S.config(c, M=M, N=M, views=1, width=W, height=H)
     R = sc.params.radius
     prm = lp.GenParams(M=M, N=M, radius=R)
@@ -466,23 +460,55 @@ def test_lookup_adjoint_full_resolution(lp, orc, c, M, W, H, K):
     sel = pix[mask.reshape(-1)[pix[:, 2].astype(np.int64) * W + pix[:, 1]]]
     # pixels inside an FP32 decision band of the neighbour search (either
     # neighbour set may differ from FP64) keep a zero adjoint
-    _, _, mg = orc.lookup(np.zeros((M, M, 3), np.float32), sc.params, sc.cams, W, H, K, sel)
+    _, onn, mg = orc.lookup(np.zeros((M, M, 3), np.float32), sc.params, sc.cams, W, H, K, sel)
     clear = (mg[:, 0] > 1e-4) & (mg[:, 1] > BAND) & (mg[:, 2] > 1e-3) & ((mg[:, 3] > BAND) | (K == 1))
     assert clear.mean() > 0.97
-    keep = sel[clear]
+    keep, knn = sel[clear], onn[clear]
     vals = rng.standard_normal((len(keep), 3)).astype(np.float32)
+    if n_inf:
+        hits = np.nonzero(knn[:, 0] >= 0)[0]
+        vals[rng.choice(hits, n_inf, replace=False), 0] = np.inf
     dimg = np.zeros((1, H, W, 3), np.float32)
     dimg[0, keep[:, 2], keep[:, 1]] = vals
     d_lf = lp.lookup_adjoint(torch.from_numpy(dimg).cuda(), prm, cams, K)
     torch.cuda.synchronize()
     ref = orc.lookup_adjoint(sc.params, sc.cams, W, H, K, keep, vals.astype(np.float64))
     got = d_lf.reshape(-1).cpu().numpy().astype(np.float64)
+    return got, ref
+
+
+@pytest.mark.parametrize("c,M,W,H,K", [(5, 1024, 512, 512, 5), (2, 2048, 1920, 1080, 5),
+                                       (2, 2048, 1920, 1080, 1), (2, 2048, 1920, 1080, 9)])
+def test_lookup_adjoint_full_resolution(lp, orc, c, M, W, H, K):
+    """At the workloads' view sizes the 64 pixels of a wave share a handful of
+    neighbours, and the scatter runs as a dense contraction per wave (MFMA)
+    over the wave's distinct origin and direction texels; waves with more
+    distinct texels (K = 9 always) take the per-pair path.  Silhouette
+    tiles are where front and back hits meet the same SF point and
+    degenerate pairs occur; the oracle transposes the selected pixels only
+    (the other pixels still enter the waves' neighbour dictionaries)."""
+    got, ref = full_resolution_adjoint(lp, orc, c, M, W, H, K)
     assert np.count_nonzero(ref) > 1000
     # the lookup's bar: FP32 view rays move each tent weight by ~1e-6 / r
     r = math.sqrt(4 * math.pi / M)
     assert np.linalg.norm(got - ref) <= LOOKUP_C / r * np.linalg.norm(ref)
     # texels no selected pixel reaches stay exactly zero
     assert np.all(got[ref == 0.0] == 0.0)
+
+
+def test_lookup_adjoint_infinite_values(lp, orc):
+    """A wave holding a non-finite adjoint value takes the per-pair path: the
+    infinities reach exactly the texels their pixels weight, as in the
+    oracle, and no NaN appears (in the dense contraction a zero weight times
+    an infinite value would spread NaN over the wave's other texels)."""
+    M = 1024
+    got, ref = full_resolution_adjoint(lp, orc, 5, M, 512, 512, 5, n_inf=6)
+    inf = np.isinf(ref)
+    assert 6 <= inf.sum() and not np.isnan(ref).any()
+    assert np.array_equal(np.isinf(got), inf) and not np.isnan(got).any()
+    fin = ~inf
+    r = math.sqrt(4 * math.pi / M)
+    assert np.linalg.norm(got[fin] - ref[fin]) <= LOOKUP_C / r * np.linalg.norm(ref[fin])
 
 
 # ------------------------------------------------- upper-hemisphere origins
