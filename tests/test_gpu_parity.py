@@ -404,7 +404,7 @@ def test_lookup_c2_full_size_sampled(lp, orc):
     check_pixels(g_img[clear], rgb[clear], tol)
 
 
-@pytest.mark.parametrize("M,N,K", [(96, 80, 5), (64, 64, 5), (64, 64, 1), (96, 80, 9)])
+@pytest.mark.parametrize("M,N,K", [(96, 80, 5), (64, 64, 5), (64, 64, 1), (96, 80, 9), (64, 64, 3), (96, 80, 2)])
 def test_lookup_adjoint(lp, orc, M, N, K):
     V, W, H = 2, 40, 30
     sc = S.config(1, M=M, N=N, views=V, width=W, height=H)
@@ -478,7 +478,8 @@ def full_resolution_adjoint(lp, orc, c, M, W, H, K, n_inf=0):
 
 
 @pytest.mark.parametrize("c,M,W,H,K", [(5, 1024, 512, 512, 5), (2, 2048, 1920, 1080, 5),
-                                       (2, 2048, 1920, 1080, 1), (2, 2048, 1920, 1080, 9)])
+                                       (2, 2048, 1920, 1080, 1), (2, 2048, 1920, 1080, 9),
+                                       (5, 1024, 512, 512, 3)])
 def test_lookup_adjoint_full_resolution(lp, orc, c, M, W, H, K):
     """At the workloads' view sizes the 64 pixels of a wave share a handful of
     neighbours, and the scatter runs as a dense contraction per wave (MFMA)
