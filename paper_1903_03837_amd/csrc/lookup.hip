@@ -373,8 +373,12 @@ __global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) 
     lookup_adjoint_pixel<KMAX, DT, L2>(P, lds[wave], px, py, blockIdx.z);
 }
 
+// Latency-bound (VALU issue ~14 %): K <= 5 is held to 6 waves per SIMD (80
+// VGPRs, no spills; 5 waves at the compiler's own 85 VGPRs), 7 % faster.
+// At 8 waves it spills; K = 9 spills at either bound and keeps the default.
 template <int KMAX, int DT>
-__global__ __launch_bounds__(256) void lookup_kernel(LookupParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ? 6 : 1))) void lookup_kernel(
+    LookupParams P) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
