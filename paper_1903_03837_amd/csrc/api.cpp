@@ -51,17 +51,18 @@ long long stored_rows(const lf_gen_params* p) { return p->origin_rows > 0 ? p->o
 
 // Sample ranges per ray (log2) of the path tracer's work items.  The
 // adjoint (rays with a nonzero adjoint only, often a small share of the
-// field) takes ranges of 8 samples, at most 16 per ray.  A forward takes at
-// most 4 ranges from 32 samples, 2 from 16; it keeps each range's sum
-// (12 bytes) until a second kernel adds them; it splits by the rays per lane
+// field) takes at most 16 ranges per ray of at least 2 samples each.  A
+// forward takes at most 4 ranges from 32 samples, 2 from 16; it keeps each
+// range's sum (12 bytes) until a second kernel adds them; it splits by the
+// rays per lane
 // of a nominal full grid (256 CUs x 3 waves x 4 SIMDs x 64 lanes = 196608):
 // 4 ranges below 8 rays per lane, 2 below 64, else 1, and never when
 // M*N*spp > 2^31.  The rule depends on M, N and spp only, so the field does
 // not depend on the device or the row split.
 int part_log2(const lf_gen_params* p, bool forward) {
-    if (!forward) {  // adjoint: ranges of 8 samples, at most 16 per ray
+    if (!forward) {  // adjoint: at most 16 ranges per ray, at least 2 samples each
         int l = 0;
-        while (l < 4 && (p->spp >> (l + 1)) >= 8) ++l;
+        while (l < 4 && (p->spp >> (l + 1)) >= 2) ++l;
         return l;
     }
     const int by_spp = p->spp >= 32 ? 2 : (p->spp >= 16 ? 1 : 0);
