@@ -23,6 +23,7 @@ import pytest
 import torch
 
 import lfsynth as S
+import radiance_bars as bars
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +31,9 @@ RAD_TOL = 1e-3
 # FP32 band of the nearest / K-th decisions, relative to the area per point
 BAND = 1e-4
 LOOKUP_C = 3e-5
+# bounds on the share of flipped values (see radiance_bars), a few times the
+# rate measured on MI355X for each workload
+FLIPS = {"c1": 2e-3, "c2": 2e-3, "c5": 2e-3}
 
 
 def lookup_tol(M, N, lf):
@@ -140,34 +144,29 @@ def test_generate_c1_full(lp, orc):
     ref, ost = orc.generate(sc, ks, stats=True)
     assert np.all(got[ks[(ks // 256) == (ks % 256)]] == 0.0)
     nd = nondegenerate(256, 256, ks)
-    err = rel_l1(got[nd], ref[nd])
-    flips = int((np.abs(got[nd] - ref[nd]).max(1) > 1e-2 * np.maximum(ref[nd].max(1), 1e-3)).sum())
-    print(f"c1: rel L1 {err:.3e}, flip texels {flips}, collisions/sample GPU {st[0] / st[3]:.3f} "
-          f"oracle {ost[0] / ost[3]:.3f}")
-    assert err <= RAD_TOL
+    print(f"c1: collisions/sample GPU {st[0] / st[3]:.3f} oracle {ost[0] / ost[3]:.3f}")
+    bars.check(got[nd], ref[nd], FLIPS["c1"], "c1 (all rays)")
     assert st[3] == ost[3]
     assert abs(st[0] / ost[0] - 1) < 1e-3 and abs(st[1] / ost[1] - 1) < 1e-3
 
 
-def test_generate_c5_subset(lp, orc):
-    """Differentiation workload (f32 volume), 4000 sampled rays."""
+def test_generate_c5_sampled(lp, orc):
+    """Differentiation workload (f32 volume) at full size, 20000 sampled rays."""
     sc = S.config(5)
     got = gpu_field(lp, sc)
-    ks = S.random_rays(1024, 1024, 4000, 55)
+    ks = S.random_rays(1024, 1024, 20000, 55)
     ref = orc.generate(sc, ks)
-    assert rel_l1(got[ks], ref) <= RAD_TOL
+    bars.check(got[ks], ref, FLIPS["c5"], "c5 (20000 rays)")
 
 
 def test_generate_c2_full_size_sampled(lp, orc):
     """CT-like workload at full size (4.19M rays, 64 spp, 8 bounces, area
-    light), in the configuration the benchmark times; 1500 sampled rays."""
+    light), in the configuration the benchmark times; 20000 sampled rays."""
     sc = S.config(2)
     got = gpu_field(lp, sc)
-    ks = S.random_rays(2048, 2048, 1500, 22)
+    ks = S.random_rays(2048, 2048, 20000, 22)
     ref = orc.generate(sc, ks)
-    err = rel_l1(got[ks], ref)
-    print(f"c2 sampled rel L1 {err:.3e}")
-    assert err <= RAD_TOL
+    bars.check(got[ks], ref, FLIPS["c2"], "c2 (20000 rays)")
     assert np.all(np.isfinite(got))
 
 
