@@ -14,7 +14,8 @@
  *  - Every array argument is device memory owned by the caller unless marked
  *    "host".  Structs passed by pointer are host memory, read during the call
  *    only.  The library allocates nothing and keeps no state between calls
- *    apart from the thread-local error message.
+ *    apart from the thread-local error message (and the fixed device scratch
+ *    of lf_lookup_static, whose contents no call relies on).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
  *    asynchronous and stream-ordered; the caller keeps buffers alive until
  *    the stream has passed the call.
@@ -216,6 +217,24 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
 int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
               int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out, void* ws,
               size_t* ws_bytes, void* stream);
+
+/* lf_lookup without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and errors as for lf_lookup, minus
+ * ws / ws_bytes: the point tables of both SF sets live in a fixed 2 MiB
+ * device array of the library (room for 2 x 65536 points, so every valid
+ * M, N fits; larger tables would be rejected with LF_E_RANGE), which each
+ * device holds from its first call until the process ends.  The first call
+ * on a device looks up that array's address with the device current; the
+ * call allocates nothing.  `stream` must belong to the current device
+ * (LF_E_ARG otherwise).  Every call overwrites the whole table it uses
+ * before reading it, so nothing carries over from an earlier call; but all
+ * calls on one device share the array, so calls that overlap in time on one
+ * device (different streams, or threads) race and must be serialised by the
+ * caller. */
+int lf_lookup_static(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams,
+                     int32_t n_views, int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf,
+                     int32_t* nn_out, void* stream);
 
 /* Lookup, loss gradient and adjoint in one pass (Sec. 2 lookup and its
  * transpose, for an L2 image loss): img receives the views of lf exactly as

@@ -96,6 +96,8 @@ def library():
         L.lf_generate_backward.argtypes = [P, P, P, P, P, P, P, P, C.POINTER(C.c_size_t), P]
         L.lf_lookup.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 P, P, P, P, C.POINTER(C.c_size_t), P]
+        L.lf_lookup_static.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_int32, P, P, P, P]
         L.lf_lookup_l2.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, P,
                                    C.POINTER(C.c_size_t), P]
         L.lf_majorant_grid.argtypes = [P, P, P, P, P]
@@ -103,7 +105,7 @@ def library():
                                       C.POINTER(C.c_size_t), P]
         L.lf_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.POINTER(C.c_size_t), P]
         L.lf_cw_ssim.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.POINTER(C.c_size_t), P]
-        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_lookup_l2,
+        for f in (L.lf_points, L.lf_generate, L.lf_generate_backward, L.lf_lookup, L.lf_lookup_static, L.lf_lookup_l2,
                   L.lf_majorant_grid, L.lf_render_views, L.lf_ssim, L.lf_cw_ssim):
             f.restype = C.c_int
         _lib = L
@@ -417,6 +419,26 @@ def lookup(lf: torch.Tensor, prm: GenParams, cams: Sequence[Camera], width: int,
     ws, sz = _workspace(library().lf_lookup, *args)
     _check(library().lf_lookup(*args, _ptr(ws), C.byref(sz), _stream()))
     return (img, nn) if with_nn else img
+
+
+def lookup_static(lf: Optional[torch.Tensor], prm: GenParams, cams: Sequence[Camera], width: int, height: int,
+                  K: int, mode: int, img: torch.Tensor, d_lf: Optional[torch.Tensor] = None,
+                  nn: Optional[torch.Tensor] = None) -> None:
+    """lf_lookup_static: lf_lookup with the library's fixed scratch (no
+    workspace).  Every buffer is the caller's: mode 0 writes img (and nn),
+    mode 1 adds the transpose of img to d_lf."""
+    V = len(cams)
+    dt = 0 if lf is None else {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}[lf.dtype]
+    if lf is not None:
+        _need(lf, prm.rows * prm.N * 3, lf.dtype, "lf")
+    _need(img, V * height * width * 3, torch.float32, "img")
+    if d_lf is not None:
+        _need(d_lf, prm.rows * prm.N * 3, torch.float32, "d_lf")
+    if nn is not None:
+        _need(nn, V * height * width * 2, torch.int32, "nn")
+    p = prm.c()
+    _check(library().lf_lookup_static(_ptr(lf), dt, C.byref(p), _cams(cams), V, width, height, K, mode,
+                                      _ptr(img), _ptr(d_lf), _ptr(nn), _stream()))
 
 
 def lookup_adjoint(dimg: torch.Tensor, prm: GenParams, cams: Sequence[Camera], K: int = 5,

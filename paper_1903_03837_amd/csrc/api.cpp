@@ -770,6 +770,36 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
                       stream);
 }
 
+int lf_lookup_static(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams,
+                     int32_t n_views, int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf,
+                     int32_t* nn_out, void* stream) {
+    g_err.clear();
+    if (mode != LF_LOOKUP_FORWARD && mode != LF_LOOKUP_ADJOINT) return fail(LF_E_ARG, "unknown mode %d", mode);
+    int r;
+    if ((r = check_params(params, false))) return r;
+    const size_t need = align256(16 * (size_t)params->M) + align256(16 * (size_t)params->N);
+    if (need > lp::kLookupScratchBytes)
+        return fail(LF_E_RANGE, "lf_lookup_static: the point tables need %zu bytes, above its fixed scratch of %zu",
+                    need, lp::kLookupScratchBytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "lf_lookup_static (current device)");
+    if (stream) {
+        hipDevice_t sdev = 0;
+        e = hipStreamGetDevice((hipStream_t)stream, &sdev);
+        if (e != hipSuccess) return hip_fail(e, "lf_lookup_static (stream device)");
+        if ((int)sdev != dev)
+            return fail(LF_E_ARG, "lf_lookup_static: the stream belongs to device %d, device %d is current",
+                        (int)sdev, dev);
+    }
+    void* ws = nullptr;
+    e = lp::lookup_scratch(dev, &ws);
+    if (e != hipSuccess) return hip_fail(e, "lf_lookup_static (scratch address)");
+    size_t ws_bytes = lp::kLookupScratchBytes;
+    return run_lookup(lf, dtype, params, cams, n_views, W, H, K, mode, img, nullptr, d_lf, nn_out, ws, &ws_bytes,
+                      stream);
+}
+
 int lf_lookup_l2(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
                  int32_t W, int32_t H, int32_t K, const float* target, float* img, float* d_lf, void* ws,
                  size_t* ws_bytes, void* stream) {

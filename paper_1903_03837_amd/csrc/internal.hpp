@@ -92,6 +92,14 @@ hipError_t launch_generate_wave(const TraceParams& P, int vtype, int mode, hipSt
 hipError_t launch_active_rays(const TraceParams& P, hipStream_t s);
 hipError_t launch_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s);
+// Fixed device scratch of lf_lookup_static (lookup.hip): room for the point
+// tables of two SF sets of up to 65536 points each.  lookup_scratch() gives
+// its address on device `dev`, which must be the current device on the first
+// call for that device.
+constexpr size_t kLookupScratchPoints = 2 * 65536;
+constexpr size_t kLookupScratchBytes = kLookupScratchPoints * 16;
+constexpr int kMaxScratchDevices = 64;
+hipError_t lookup_scratch(int dev, void** ptr);
 hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s);
 hipError_t launch_combine_parts(const TraceParams& P, hipStream_t s);
 // Table of the n SF points sf_point(n, i, inv_n) as float4 (w = 0).

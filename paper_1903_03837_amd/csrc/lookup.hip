@@ -16,6 +16,8 @@
 // float atomic per channel is issued per distinct texel either way.
 #include <hip/hip_fp16.h>
 
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace lp {
@@ -514,6 +516,31 @@ hipError_t launch_sf_table(int n, float inv_n, float4* out, hipStream_t s) {
 hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s) {
     hipError_t e = launch_sf_table(P.M, P.invM, (float4*)P.tab_o, s);
     return e == hipSuccess ? launch_sf_table(P.N, P.invN, (float4*)P.tab_d, s) : e;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of the lookup entry point that allocates nothing: the point
+// tables of both SF sets, 16 bytes per point, each set below 65536 points
+// (2 MiB per device, held until the process ends).  Host code never passes
+// `scratch` itself to a kernel (on the host it names a stand-in, not device
+// memory): the address each device gives for it is looked up once per
+// device, with that device current, and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float4 scratch[kLookupScratchPoints];
+
+hipError_t lookup_scratch(int dev, void** ptr) {
+    static std::mutex mu;
+    static void* addr[kMaxScratchDevices] = {};
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s) {
