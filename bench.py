@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the LumiPath light-field path on one MI355X.
 
-One step = one pass of the whole path over the CT-like workload (256^3 u16
-phantom, M = N = 2048 spherical-Fibonacci points, 4.19M rays, 64 samples per
-ray, 8 bounces, HG g = 0.3, area light):
-  lf_points (SF table) -> lf_generate (FP32 light field, 5^3 majorant grid, keeping
-  every sample's radiance) -> lf_lookup_l2 (32 views of 1920 x 1080, K = 5, the
-  gradient of 1/2 |views - targets|^2 and its lookup transpose, in one pass) ->
-  lf_generate_backward (d LUT, d density scale; one replay per sample, from the
-  kept radiance).
-`value` = M*N*spp path samples per second of the whole step.  One JSON line
-on stdout; progress on stderr.  Inputs are seeded synthetic data (lfsynth).
+The timed step runs on the precision workload, the largest one a single GPU
+holds: 512^3 u16 CT-like phantom (40 nested ellipsoids) in 8^3 bricks,
+M = N = 32768 spherical-Fibonacci points (1.07B rays), 16 samples per ray,
+8 bounces, HG g = 0.3, area light, 8^3 majorant grid:
+  lf_points (SF table) -> lf_generate (FP32 light field, 12.9 GB) -> lf_lookup
+  (32 views of 1920 x 1080, K = 5).
+`value` = M*N*spp path samples per second of that step.  Next to it: the
+same field stored as FP16 and BF16 (time, memory, error against the FP64
+oracle on a seeded 1 % ray subset), the CT-like step with the adjoint
+(256^3 phantom, N = 2048, 64 spp: generation keeping each sample's radiance,
+lookup fused with an L2 loss gradient and its transpose, path-replay adjoint;
+only rays the views reach carry an adjoint), and the dense adjoint of the
+differentiation workload (128^3 f32, N = 1024, 32 spp: every ray carries an
+adjoint, two replays per sample).  One JSON line on stdout; progress on
+stderr.  Inputs are seeded synthetic data (lfsynth).
 """
 import argparse
 import dataclasses
@@ -23,17 +28,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic 32-bit ALU operations per unit of work (see the design notes,
-# "roofline of generation"): counted from the estimator's definition, one op
-# per add/mul/fma/compare/convert/logic, four per transcendental, 60 per
-# Philox4x32-10 block (10 rounds x (2 wide multiplies + 4 xor)).
-OPS_TENTATIVE = 113     # free-flight step: 1/2 Philox, log, trilinear fetch, classify, accept
-OPS_SHADOW = 90         # ratio-tracking step: 1/4 Philox, log, trilinear fetch, alpha, Tr update
-OPS_REAL = 270          # scatter vertex: albedo, Philox block, light sample, phase eval/sample, clips
-OPS_SAMPLE = 140        # jitter (Philox block, sqrt, sincos, frame), first clip, escape, accumulate
-OPS_RAY = 80            # two SF points (FP64 frac), direction, store
-OPS_CELL = 16           # majorant-grid step: cell majorant read, 3-way min, spend/compare, advance
-PEAK_OPS = 256 * 4 * 16 * 2.4e9   # 32-bit lane ops per second: CUs x SIMDs x lanes x clock
+# Algorithmic work of generation per tentative point (a delta-tracking
+# collision or a ratio-tracking step): ~40 FP32 operations (position,
+# trilinear interpolation, classification, accept or transmittance update),
+# one Philox4x32-10 call (60 32-bit operations: 10 rounds of 2 wide
+# multiplies and 4 xors) and one logarithm (4).  Peak: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz, one 32-bit lane operation per lane and clock.
+OPS_POINT = 40 + 60 + 4
+PEAK_OPS = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
 
 
@@ -50,40 +52,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash):
-    """HBM bytes per generation launch from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "gen_c2_traffic.json")
+def measured_traffic(kernel_hash, name):
+    """HBM bytes per generation launch from a committed rocprofv3 PMC summary,
+    if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_hash") != kernel_hash:
         return None
     return d.get("hbm_bytes_per_launch")
-
-
-def cpu_baseline(scene, seconds, nrays_probe=20000):
-    """The FP64 oracle on a bounded seeded sample of the same rays."""
-    import numpy as np
-
-    import lfsynth as S
-    from oracle import oracle as orc
-
-    threads = orc.default_threads()
-    M, N = scene.params.M, scene.params.N
-    ks = S.random_rays(M, N, nrays_probe, 777)
-    t0 = time.perf_counter()
-    orc.generate(scene, ks, nthreads=threads)
-    dt = time.perf_counter() - t0
-    n = int(min(M * N, max(nrays_probe, nrays_probe * seconds / max(dt, 1e-3))))
-    ks = S.random_rays(M, N, n, 778)
-    t0 = time.perf_counter()
-    ref = orc.generate(scene, ks, nthreads=threads)
-    dt = time.perf_counter() - t0
-    samples = len(ks) * scene.params.spp
-    return {"value": samples / dt, "unit": "path samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(ks)} seeded random rays of the same workload x {scene.params.spp} spp "
-                      f"({dt:.1f} s, FP64 C, pthreads)"}, ks, ref
 
 
 def sweep_configs(configs, with_oracle=True, calib_copy_mb=0):
@@ -253,13 +231,177 @@ def sweep_configs(configs, with_oracle=True, calib_copy_mb=0):
         torch.cuda.synchronize()
 
 
+def timed_ms(fn, reps, stream):
+    import numpy as np
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def missing_rays(prm, pad):
+    """Rays of the SF ray set whose chord misses the volume box grown by
+    `pad` (FP64, on the GPU in row chunks): the generation kernel finishes
+    them without tracing (their samples are the environment)."""
+    import math
+    import torch
+    dev = "cuda"
+    phi = (math.sqrt(5.0) - 1.0) / 2.0
+
+    def sf(n):
+        i = torch.arange(n, dtype=torch.float64, device=dev)
+        z = 1.0 - (2.0 * i + 1.0) / n
+        st = torch.sqrt(torch.clamp(1.0 - z * z, min=0.0))
+        ph = 2.0 * math.pi * torch.frac(i * phi)
+        return torch.stack([torch.cos(ph) * st, torch.sin(ph) * st, z], 1)
+
+    po, pd = sf(prm.M), sf(prm.N)
+    lo, hi = -1.0 - pad, 1.0 + pad
+    R = prm.radius
+    count = 0
+    for r0 in range(0, prm.rows, 1024):
+        o = po[r0:min(prm.rows, r0 + 1024)]
+        d = pd[None, :, :] - o[:, None, :]
+        d = d / torch.clamp(d.norm(dim=-1, keepdim=True), min=1e-300)
+        x = (R * o)[:, None, :]
+        with torch.no_grad():
+            t1 = (lo - x) / d
+            t2 = (hi - x) / d
+        tn = torch.clamp(torch.nan_to_num(torch.minimum(t1, t2), nan=-1e300).amax(-1), min=0.0)
+        tf = torch.nan_to_num(torch.maximum(t1, t2), nan=1e300).amin(-1)
+        miss = ~(tn < tf)
+        if prm.M == prm.N:  # texels i == j have no direction and are not traced either
+            idx = torch.arange(o.shape[0], device=dev)
+            miss[idx, r0 + idx] = False
+        count += int(miss.sum())
+        del d, t1, t2
+    return count
+
+
+def c2_step_extra(steps, warmup):
+    """The CT-like step with the adjoint (extra keys of the bench line)."""
+    import numpy as np
+    import torch
+
+    import lfsynth as S
+    import paper_1903_03837_amd as lp
+
+    dev = "cuda"
+    sc = S.config(2)
+    vol, med, light, prm, cams = lp.device_scene(sc)
+    V, W, H, K = len(cams), sc.width, sc.height, sc.K
+    M, N, spp = prm.M, prm.N, prm.spp
+    lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
+    img = torch.empty((V, H, W, 3), dtype=torch.float32, device=dev)
+    d_lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
+    srad = torch.empty((M, N, spp, 3), dtype=torch.float32, device=dev)
+    tm = S.target_medium(sc)
+    tmed = lp.Medium(torch.from_numpy(tm.lut).to(dev), tm.scale)
+    target = lp.lookup(lp.generate(vol, tmed, light, prm), prm, cams, W, H, K)
+    stream = torch.cuda.current_stream()
+
+    def step(evs):
+        evs[0].record(stream)
+        lp.points(M)
+        evs[1].record(stream)
+        lp.generate(vol, med, light, prm, out=lf, sample_radiance=srad)
+        evs[2].record(stream)
+        d_lf.zero_()
+        lp.lookup_l2(lf, prm, cams, target, K, img=img, d_lf=d_lf)
+        evs[3].record(stream)
+        lp.generate_backward(vol, med, light, prm, d_lf, sample_radiance=srad)
+        evs[4].record(stream)
+
+    for _ in range(warmup):
+        step([torch.cuda.Event(enable_timing=True) for _ in range(5)])
+    torch.cuda.synchronize()
+    all_evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(all_evs[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    names = ["points", "generate", "lookup_loss_adjoint", "generate_backward"]
+    legs = {nm: float(np.mean([e[a].elapsed_time(e[a + 1]) for e in all_evs])) for a, nm in enumerate(names)}
+    listed = int((d_lf.abs().sum(-1) != 0).sum())
+    # the same adjoint tracing each sample twice (no kept radiance)
+    bwd2 = timed_ms(lambda: lp.generate_backward(vol, med, light, prm, d_lf), 3, stream)
+    gen_plain = timed_ms(lambda: lp.generate(vol, med, light, prm, out=lf), 3, stream)
+    lookup_ms = timed_ms(lambda: lp.lookup(lf, prm, cams, W, H, K, img=img), 3, stream)
+    # image quality against path-traced views (4 of the views at 480 x 270, 256 spp)
+    qv, qw, qh, qspp = 4, 480, 270, 256
+    qcams = cams[:qv]
+    gt_prm = dataclasses.replace(prm, spp=qspp)
+    gt = lp.render_views(vol, med, light, gt_prm, qcams, qw, qh)
+    render_ms = timed_ms(lambda: lp.render_views(vol, med, light, gt_prm, qcams, qw, qh, img=gt), 1, stream)
+    gmax = float(gt.max())
+    quality = {"views": qv, "width": qw, "height": qh, "ground_truth_spp": qspp, "render_ms": render_ms,
+               "render_samples_per_s": qv * qw * qh * qspp / (render_ms / 1e3)}
+    for kk in (1, K):
+        v_img = lp.lookup(lf, prm, qcams, qw, qh, kk)
+        quality[f"ssim_K{kk}"] = float(lp.ssim(v_img, gt, data_range=gmax).mean())
+        quality[f"cw_ssim_K{kk}"] = float(lp.cw_ssim(v_img, gt, data_range=gmax).mean())
+        quality[f"rel_l1_K{kk}"] = float((v_img - gt).abs().sum() / gt.abs().sum())
+    out = {
+        "workload": "CT-like phantom 256^3 u16, M=N=2048 (4.19M rays), 64 spp, 8 bounces, HG g=0.3, area light, "
+                    "5^3 majorant grid; FP32 field keeping each sample's radiance; lookup of 32 views 1920x1080 "
+                    "K=5 fused with the loss 1/2 |views - targets|^2 and its transpose; path-replay adjoint",
+        "steps": steps, "ms_per_step": ms, "path_samples_per_s": M * N * spp / (ms / 1e3), "legs_ms": legs,
+        "generate_ms_without_kept_radiance": gen_plain, "lookup_ms": lookup_ms,
+        "lookup_pixels_per_s": V * W * H / (lookup_ms / 1e3),
+        "adjoint_rays": listed, "adjoint_rays_frac": listed / (M * N),
+        "adjoint_forward_ratio_sparse": legs["generate_backward"] / legs["generate"],
+        "adjoint_two_replays_ms": bwd2,
+        "adjoint_forward_ratio_sparse_two_replays": bwd2 / gen_plain,
+        "quality_vs_ground_truth": quality,
+    }
+    del srad, lf, img, d_lf, target
+    torch.cuda.empty_cache()
+    return out
+
+
+def c5_dense_adjoint():
+    """Differentiation workload: forward, and the adjoint with every
+    non-degenerate ray carrying a (seeded) adjoint value: two replays per
+    sample, nothing kept from the forward."""
+    import numpy as np
+    import torch
+
+    import lfsynth as S
+    import paper_1903_03837_amd as lp
+
+    sc = S.config(5)
+    vol, med, light, prm, cams = lp.device_scene(sc)
+    M, N = prm.M, prm.N
+    stream = torch.cuda.current_stream()
+    lf = lp.generate(vol, med, light, prm)
+    fwd = timed_ms(lambda: lp.generate(vol, med, light, prm, out=lf), 5, stream)
+    g = torch.Generator(device="cuda").manual_seed(505)
+    d_lf = torch.randn((M, N, 3), generator=g, device="cuda")
+    d_lf.view(M * N, 3)[torch.arange(M, device="cuda") * (N + 1)] = 0.0
+    lp.generate_backward(vol, med, light, prm, d_lf)
+    bwd = timed_ms(lambda: lp.generate_backward(vol, med, light, prm, d_lf), 5, stream)
+    return {"workload": "128^3 f32 blobs, M=N=1024, 32 spp, 4 bounces, directional light, 8^3 majorant grid; "
+                        "seeded adjoint on every non-degenerate ray",
+            "forward_ms": fwd, "adjoint_ms": bwd, "adjoint_forward_ratio_dense": bwd / fwd}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed step (for profiler runs)")
+    ap.add_argument("--subset-frac", type=float, default=0.01,
+                    help="share of the rays in the seeded subset the oracle traces")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--configs", type=str, default="",
@@ -274,6 +416,8 @@ def main():
                       calib_copy_mb=args.calib_copy_mb)
         return
 
+    import math
+
     import numpy as np
     import torch
 
@@ -282,123 +426,93 @@ def main():
 
     torch.cuda.set_device(0)
     lp.library()
-    log("bench: building the CT-like workload (256^3 u16 phantom, N=2048, 64 spp)")
-    sc = S.config(2)
+    dev = "cuda"
+    log("bench: building the precision workload (512^3 u16 phantom in 8^3 bricks, N=32768, 16 spp)")
+    sc = S.config(4, views=32, width=1920, height=1080)
     vol, med, light, prm, cams = lp.device_scene(sc)
     V, W, H, K = len(cams), sc.width, sc.height, sc.K
     M, N, spp = prm.M, prm.N, prm.spp
-    dev = "cuda"
     lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
     img = torch.empty((V, H, W, 3), dtype=torch.float32, device=dev)
-    dimg = torch.empty_like(img)
-    d_lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
-    # every sample's radiance, kept by the forward for the adjoint (3.2 GB)
-    srad = torch.empty((M, N, spp, 3), dtype=torch.float32, device=dev)
-
-    # seeded target views: the same scene under the perturbed medium
-    tm = S.target_medium(sc)
-    tmed = lp.Medium(torch.from_numpy(tm.lut).to(dev), tm.scale)
-    target = lp.lookup(lp.generate(vol, tmed, light, prm), prm, cams, W, H, K)
-
-    # counts of the units of work (deterministic for the fixed stream)
-    stats = torch.zeros(5, dtype=torch.int64, device=dev)
-    lp.generate(vol, med, light, prm, out=lf, stats=stats)
-    torch.cuda.synchronize()
-    tent, shadow, real, samples, cells = (int(x) for x in stats.cpu().numpy())
-    rays = M * N - (M if M == N else 0)
-    alg_ops = (tent * OPS_TENTATIVE + shadow * OPS_SHADOW + real * OPS_REAL + samples * OPS_SAMPLE
-               + rays * OPS_RAY + cells * OPS_CELL)
-
     stream = torch.cuda.current_stream()
-    nev = 5
 
     def step(evs):
         evs[0].record(stream)
         lp.points(M)
         evs[1].record(stream)
-        lp.generate(vol, med, light, prm, out=lf, sample_radiance=srad)
+        lp.generate(vol, med, light, prm, out=lf)
         evs[2].record(stream)
-        # views, the gradient of 1/2 |views - targets|^2 and its transpose, in one pass
-        d_lf.zero_()
-        lp.lookup_l2(lf, prm, cams, target, K, img=img, d_lf=d_lf)
+        lp.lookup(lf, prm, cams, W, H, K, img=img)
         evs[3].record(stream)
-        d_lut, d_scale = lp.generate_backward(vol, med, light, prm, d_lf, sample_radiance=srad)
-        evs[4].record(stream)
-        return d_lut, d_scale
 
     log(f"bench: {args.warmup} warmup + {args.steps} timed steps")
     for _ in range(args.warmup):
-        step([torch.cuda.Event(enable_timing=True) for _ in range(nev)])
+        step([torch.cuda.Event(enable_timing=True) for _ in range(4)])
+        torch.cuda.synchronize()
+        log("bench: warmup step done")
+    all_evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
-    all_evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(all_evs[s])
+    for k in range(args.steps):
+        step(all_evs[k])
+        if k % 4 == 3:  # progress (the queue stays full: the next step is already enqueued)
+            all_evs[k][3].synchronize()
+            log(f"bench: {k + 1} steps done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    legs = {}
-    names = ["points", "generate", "lookup_loss_adjoint", "generate_backward"]
-    for a, name in enumerate(names):
-        legs[name] = float(np.mean([e[a].elapsed_time(e[a + 1]) for e in all_evs]))
+    names = ["points", "generate", "lookup"]
+    legs = {nm: float(np.mean([e[a].elapsed_time(e[a + 1]) for e in all_evs])) for a, nm in enumerate(names)}
     ms_per_step = elapsed * 1e3 / args.steps
     log("bench: legs (ms) " + ", ".join(f"{k} {v:.2f}" for k, v in legs.items()))
-
-    # the plain lookup alone (outside the timed step), for its own throughput
-    lk = []
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        lp.lookup(lf, prm, cams, W, H, K, img=dimg)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        lk.append(e0.elapsed_time(e1))
-    lookup_ms = float(np.median(lk))
-
     gen_s = legs["generate"] / 1e3
-    # voxel bytes the estimator reads: 8 voxels per tentative point (u16)
-    tent_bytes = (tent + shadow) * 8 * 2
-    achieved = alg_ops / gen_s
     khash = kernel_source_hash()
-    traffic = measured_traffic(khash)
 
-    # storage precision: FP16 / BF16 fields against the FP32 field
-    f32 = lf.clone()
-    f16 = lp.generate(vol, med, light, prm, dtype="f16").float()
-    b16 = lp.generate(vol, med, light, prm, dtype="bf16").float()
-    torch.cuda.synchronize()
-    denom = f32.abs().sum().item()
-    err16 = (f16 - f32).abs().sum().item() / denom
-    errb16 = (b16 - f32).abs().sum().item() / denom
+    if args.no_extras:
+        print(json.dumps({"metric": "LF path samples/s + %HBM roofline; FP16 vs FP32 err; adjoint/forward time",
+                          "value": M * N * spp / (ms_per_step / 1e3), "unit": "path samples/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+                          "legs_ms": legs, "kernel_hash": khash}), flush=True)
+        return
 
-    # image quality against path-traced views (not part of the timed step):
-    # 4 of the views at 480 x 270, ground truth at 256 spp
-    qv, qw, qh, qspp = 4, 480, 270, 256
-    qcams = cams[:qv]
-    gt_prm = dataclasses.replace(prm, spp=qspp)
-    gt = lp.render_views(vol, med, light, gt_prm, qcams, qw, qh)
+    # work counts of one launch (deterministic for the fixed stream)
+    stats = torch.zeros(5, dtype=torch.int64, device=dev)
+    lp.generate(vol, med, light, prm, out=lf, stats=stats)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    lp.render_views(vol, med, light, gt_prm, qcams, qw, qh, img=gt)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    render_ms = e0.elapsed_time(e1)
-    gmax = float(gt.max())
-    quality = {"views": qv, "width": qw, "height": qh, "ground_truth_spp": qspp,
-               "render_ms": render_ms, "render_samples_per_s": qv * qw * qh * qspp / (render_ms / 1e3)}
-    for kk in (1, K):
-        v_img = lp.lookup(lf, prm, qcams, qw, qh, kk)
-        quality[f"ssim_K{kk}"] = float(lp.ssim(v_img, gt, data_range=gmax).mean())
-        quality[f"cw_ssim_K{kk}"] = float(lp.cw_ssim(v_img, gt, data_range=gmax).mean())
-        quality[f"rel_l1_K{kk}"] = float((v_img - gt).abs().sum() / gt.abs().sum())
-    log("bench: light-field views vs ground truth " + json.dumps(quality))
+    tent, shadow, real, samples, cells = (int(x) for x in stats.cpu().numpy())
+    rays = prm.rows * N - (M if M == N else 0)
+    pad = 2.0 * prm.radius / math.sqrt(M) * 1.001 + 1e-5 * prm.radius
+    n_miss = missing_rays(prm, pad)
+    traced = (rays - n_miss) * spp
+    points = tent + shadow
+    achieved = OPS_POINT * points / gen_s
+    traffic = measured_traffic(khash, "gen_c4_traffic.json")
+    log(f"bench: {points} tentative points, {n_miss} of {rays} rays miss the box")
 
-    if args.calib_copy_mb:
-        n = args.calib_copy_mb * (1 << 20) // 4
-        a_ = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
-        b_ = torch.empty_like(a_)
-        b_.copy_(a_)
-        torch.cuda.synchronize()
+    # the same field stored as FP16 and BF16
+    low = {}
+    for name in ("f16", "bf16"):
+        t = lp.generate(vol, med, light, prm, dtype=name)
+        ms_low = timed_ms(lambda: lp.generate(vol, med, light, prm, dtype=name, out=t), 1, stream)
+        low[name] = (t, ms_low)
+        log(f"bench: {name} generation {ms_low:.1f} ms")
+
+    def rel(got, ref):
+        den = np.abs(ref).sum()
+        floor = 1e-3 * np.abs(ref).mean()
+        r = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
+        return {"rel_l1": float(np.abs(got - ref).sum() / den), "mean_rel": float(r.mean()),
+                "p99_rel": float(np.quantile(r, 0.99)), "max_rel": float(r.max()),
+                "flip_frac": float((r > 1e-2).mean()), "frac_within_1e-3": float((r <= 1e-3).mean())}
+
+    precision = {"f32": {"generate_ms": legs["generate"], "field_bytes": lf.numel() * 4}}
+    for name, (t, ms_low) in low.items():
+        f = t.float()
+        den = float(lf.abs().sum())
+        precision[name] = {"generate_ms": ms_low, "field_bytes": t.numel() * t.element_size(),
+                           "memory_vs_f32": t.numel() * t.element_size() / (lf.numel() * 4),
+                           "throughput_vs_f32": legs["generate"] / ms_low,
+                           "rel_l1_vs_f32": float((f - lf).abs().sum()) / den}
+        del f
 
     out = {
         "metric": "LF path samples/s + %HBM roofline; FP16 vs FP32 err; adjoint/forward time",
@@ -414,11 +528,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded CT-like phantom, transfer function, area light, cameras)",
         "config": {
-            "workload": "CT-like phantom 256^3 u16 (12 nested ellipsoids), M=N=2048 SF points (4.19M rays), "
-                        "64 spp, 8 bounces, HG g=0.3, area light, 5^3 majorant grid, FP32 light field; lookup of "
-                        "32 views 1920x1080 K=5 fused with the loss 1/2 |views - targets|^2 and its lookup transpose; adjoint by path replay from the forward's per-sample radiance",
+            "workload": "precision workload: CT-like phantom 512^3 u16 (40 nested ellipsoids) in 8^3 bricks, "
+                        "M=N=32768 SF points (1.07B rays), 16 spp, 8 bounces, HG g=0.3, area light, 8^3 majorant "
+                        "grid, FP32 light field (12.9 GB); lookup of 32 views 1920x1080 K=5",
             "M": M, "N": N, "spp": spp, "max_bounces": prm.max_bounces, "views": V, "width": W, "height": H,
-            "K": K, "volume": "256^3 u16 linear", "majorant_grid": prm.grid,
+            "K": K, "volume": "512^3 u16 8^3-bricked", "majorant_grid": prm.grid,
         },
         "roofline": {
             "kernel": "gen_wave_kernel<u16, forward> (lf_generate)",
@@ -428,36 +542,63 @@ def main():
             "unit": "Top/s (32-bit lane ops)",
             "frac": achieved / PEAK_OPS,
             "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_GBps": (traffic / gen_s / 1e9) if traffic else None,
-            "gather_GBps": tent_bytes / gen_s / 1e9,
+            "hbm_frac": (traffic / gen_s / PEAK_HBM) if traffic else None,
             "launch_ms": legs["generate"],
-            "ops_per_launch": alg_ops,
-            "units_per_launch": {"tentative_collisions": tent, "shadow_steps": shadow, "real_collisions": real,
-                                 "samples": samples, "rays": rays, "majorant_cell_steps": cells},
+            "ops_per_point": OPS_POINT,
+            "ops_per_launch": OPS_POINT * points,
+            "units_per_launch": {"tentative_points": points, "tentative_collisions": tent, "shadow_steps": shadow,
+                                 "real_collisions": real, "samples": samples, "traced_samples": traced,
+                                 "rays": rays, "rays_missing_the_box": n_miss, "majorant_cell_steps": cells},
         },
         "legs_ms": legs,
         "generate_samples_per_s": M * N * spp / gen_s,
-        "lookup_ms": lookup_ms,
-        "lookup_pixels_per_s": V * W * H / (lookup_ms / 1e3),
-        "lookup_gather_GBps": V * W * H * 312 / (lookup_ms / 1e3) / 1e9,
-        "adjoint_forward_ratio": legs["generate_backward"] / legs["generate"],
-        "fp16_vs_fp32_rel_err": err16,
-        "bf16_vs_fp32_rel_err": errb16,
-        "quality_vs_ground_truth": quality,
-        "collisions_per_sample": tent / samples,
-        "cell_steps_per_sample": cells / samples,
+        "traced_samples_per_s": traced / gen_s,
+        "tentative_points_per_s": points / gen_s,
+        "lookup_pixels_per_s": V * W * H / (legs["lookup"] / 1e3),
+        "precision": precision,
         "kernel_hash": khash,
     }
+    del img
+    torch.cuda.empty_cache()
+
     if not args.no_cpu_baseline:
-        log(f"bench: oracle CPU baseline (~{args.cpu_seconds:.0f} s)")
-        base, ks, ref = cpu_baseline(sc, args.cpu_seconds)
-        out["cpu_baseline"] = base
-        got = f32.reshape(-1, 3)[torch.from_numpy(ks).to(dev)].double().cpu().numpy()
-        got16 = f16.reshape(-1, 3)[torch.from_numpy(ks).to(dev)].double().cpu().numpy()
-        den = np.abs(ref).sum()
-        out["fp32_vs_oracle_rel_err"] = float(np.abs(got - ref).sum() / den)
-        out["fp16_vs_oracle_rel_err"] = float(np.abs(got16 - ref).sum() / den)
+        # the oracle on the seeded ray subset: the CPU baseline and the error
+        # of each storage type against FP64
+        from oracle import oracle as orc
+        threads = orc.default_threads()
+        ks = S.random_rays(M, N, int(M * N * args.subset_frac), 9004)
+        log(f"bench: FP64 oracle on {len(ks)} rays ({100 * args.subset_frac:g} % subset), {threads} threads")
+        t0 = time.perf_counter()
+        ref = orc.generate(sc, ks, nthreads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(ks) * spp / dt, "unit": "path samples/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"seeded {100 * args.subset_frac:g} % ray subset of the precision workload: "
+                                         f"{len(ks)} rays x {spp} spp ({dt:.1f} s, FP64 C, pthreads)"}
+        idx = torch.from_numpy(ks).to(dev)
+        for name, t in (("f32", lf), ("f16", low["f16"][0]), ("bf16", low["bf16"][0])):
+            got = t.reshape(-1, 3)[idx].double().cpu().numpy()
+            out["precision"][name]["vs_fp64_oracle"] = dict(rays=int(len(ks)), **rel(got, ref))
+        del ref
+    del low, lf
+    torch.cuda.empty_cache()
+
+    log("bench: CT-like step with the adjoint")
+    out["ct_like_step"] = c2_step_extra(max(5, args.steps // 2), 2)
+    log("bench: dense adjoint of the differentiation workload")
+    out["dense_adjoint"] = c5_dense_adjoint()
+    out["adjoint_forward_ratio_dense"] = out["dense_adjoint"]["adjoint_forward_ratio_dense"]
+    out["adjoint_forward_ratio_sparse"] = out["ct_like_step"]["adjoint_forward_ratio_sparse"]
+    out["fp16_vs_fp32_rel_err"] = out["precision"]["f16"]["rel_l1_vs_f32"]
+    out["bf16_vs_fp32_rel_err"] = out["precision"]["bf16"]["rel_l1_vs_f32"]
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        a_ = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        b_ = torch.empty_like(a_)
+        b_.copy_(a_)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -25,7 +25,9 @@ import radiance_bars as bars
 pytestmark = pytest.mark.gpu
 
 # flip-share bounds (radiance_bars), a few times the rates measured on MI355X
-FLIPS = {"c3": 2e-3, "c4": 2e-3, "paper": 2e-3}
+# (c3: 4e-4, c4: 1e-4 of the compared values; the paper's configuration: none
+# of 60000)
+FLIPS = {"c3": 1.2e-3, "c4": 5e-4, "paper": 2e-4}
 
 
 @pytest.fixture(scope="module")
@@ -60,9 +62,9 @@ def test_c3_large_bricked(lp, orc):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"c3: {dt * 1e3:.0f} ms, {8192 * 8192 * 128 / dt:.3e} samples/s")
-    ks = S.random_rays(8192, 8192, 5000, 31)
+    ks = S.random_rays(8192, 8192, 20000, 31)
     ref = orc.generate(sc, ks)
-    bars.check(sampled(lf, ks), ref, FLIPS["c3"], "c3 (5000 rays)")
+    bars.check(sampled(lf, ks), ref, FLIPS["c3"], "c3 (20000 rays)")
     assert torch.isfinite(lf).all()
 
 

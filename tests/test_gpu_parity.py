@@ -32,8 +32,9 @@ RAD_TOL = 1e-3
 BAND = 1e-4
 LOOKUP_C = 3e-5
 # bounds on the share of flipped values (see radiance_bars), a few times the
-# rate measured on MI355X for each workload
-FLIPS = {"c1": 2e-3, "c2": 2e-3, "c5": 2e-3}
+# rate measured on MI355X for each workload (c1: 0 of 195840 values; c2 and c5:
+# 3 of 60000)
+FLIPS = {"c1": 1e-4, "c2": 3e-4, "c5": 3e-4}
 
 
 def lookup_tol(M, N, lf):
