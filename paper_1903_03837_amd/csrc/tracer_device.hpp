@@ -120,6 +120,15 @@ struct TraceParams {
     unsigned int* ray_count;
 };
 
+// The kernel arguments seen through the kernarg segment (constant address
+// space): fields read through such a reference load with scalar loads.  The
+// persistent kernels read their parameters this way inside their main loop,
+// behind an empty asm barrier per iteration that keeps the loads from being
+// hoisted: the compiler then reloads parameters where they are needed
+// instead of holding ~100 uniform values in scalar registers and spilling
+// them to vector-register lanes (one VALU instruction per spilled read).
+typedef const __attribute__((address_space(4))) TraceParams KTraceParams;
+
 // Ray tiles: 8 origins x 8 directions, taken in groups of 16 origin tiles
 // sweeping the direction tiles; the tile sequence is cut into 8 parts, one
 // per XCD (workgroups are dispatched round-robin over the XCDs).
@@ -139,8 +148,12 @@ __device__ __forceinline__ void tile_coords(long long t, int tiles_i, int tiles_
     ti = (int)(gi * kGroupTiles + (off - q * gsz));
 }
 
-// Lane states of the persistent kernels.
-enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4, kShadow2 = 5, kScatter = 6 };
+// Lane states of the persistent kernels (kDone: the sample's radiance is
+// complete and waits to be added to its texel).
+enum : int { kIdle = 0, kStart = 1, kFlight = 2, kVertex = 3, kShadow = 4, kShadow2 = 5, kScatter = 6, kDone = 7 };
+// A further tracking pass runs while at least this many lanes of a wave are
+// still tracking a segment.
+constexpr int kTrackPass = 36;
 
 // Next tile for a wave whose home part is `home`; -1 when all are taken.
 __device__ __forceinline__ long long next_tile(unsigned int* ctr, long long ntiles, int home, unsigned& dry) {
@@ -188,8 +201,8 @@ __device__ __forceinline__ float vox(const void* v, uint32_t idx) {
 // (ix/3, iy/3, iz/3) at local offset (ix%3, iy%3, iz%3): one 128-byte line
 // for u16, half a line for u8, and one of two lines for f32 (or both, in one
 // case of three).  Its eight voxels sit at fixed offsets from the first.
-template <int VT>
-__device__ __forceinline__ float sample_volume(const TraceParams& P, f3 y) {
+template <int VT, class PT>
+__device__ __forceinline__ float sample_volume(const PT& P, f3 y) {
     const float gx = fminf(fmaxf(fmaf(y.x, P.ga[0], P.gb[0]), 0.0f), P.gmax[0]);
     const float gy = fminf(fmaxf(fmaf(y.y, P.ga[1], P.gb[1]), 0.0f), P.gmax[1]);
     const float gz = fminf(fmaxf(fmaf(y.z, P.ga[2], P.gb[2]), 0.0f), P.gmax[2]);
@@ -221,8 +234,8 @@ struct TF {
 };
 
 // Post-classification: window, clamp, linear LUT interpolation (LUT in LDS).
-template <int MODE>
-__device__ __forceinline__ TF classify(const TraceParams& P, const float4* lut_e, const float4* lut_s, float raw) {
+template <int MODE, class PT>
+__device__ __forceinline__ TF classify(const PT& P, const float4* lut_e, const float4* lut_s, float raw) {
     TF t;
     const float s = fminf(fmaxf((raw - P.vmin) * P.vscale, 0.0f), 1.0f);
     const float u = s * P.lut_last;
@@ -274,7 +287,8 @@ __device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, float& tn
 // than jit_rad, so the test clips against the box grown by jit_rad plus a
 // margin far above FP32 rounding; without jitter it is the sample's own clip
 // (the same function on the same origin).
-__device__ __forceinline__ bool misses_box(const TraceParams& P, f3 O, f3 bmin, f3 bmax, f3 po, f3 d0) {
+template <class PT>
+__device__ __forceinline__ bool misses_box(const PT& P, f3 O, f3 bmin, f3 bmax, f3 po, f3 d0) {
     const float pad = P.jitter ? P.jit_rad * 1.001f + 1e-5f * P.R : 0.0f;
     float tn, tf;
     return !clip_box(mk3(bmin.x - pad, bmin.y - pad, bmin.z - pad), mk3(bmax.x + pad, bmax.y + pad, bmax.z + pad),
@@ -318,9 +332,11 @@ __device__ __forceinline__ float neg_log1m(float u) { return -__logf(1.0f - u); 
 // ---------------------------------------------------------------------------
 struct GridWalk {
     float t, tx, ty, tz, dx, dy, dz;
-    int ci;  // cell index in the padded grid (one border cell per side)
+    int ci;          // cell index in the padded grid (one border cell per side)
+    int sx, sy, sz;  // signed index steps along x, y, z (by the sign of d)
 
-    __device__ __forceinline__ void init(const TraceParams& P, f3 x, f3 d, float t0) {
+    template <class PT>
+    __device__ __forceinline__ void init(const PT& P, f3 x, f3 d, float t0) {
         const int G = P.grid_n;
         const f3 p = fma3(d, t0, x);
         const float pp[3] = {p.x, p.y, p.z}, dd[3] = {d.x, d.y, d.z}, xx[3] = {x.x, x.y, x.z};
@@ -342,6 +358,9 @@ struct GridWalk {
         t = t0;
         const int Gp = G + 2;
         ci = ((c[2] + 1) * Gp + (c[1] + 1)) * Gp + (c[0] + 1);
+        sx = d.x > 0.0f ? 1 : -1;
+        sy = d.y > 0.0f ? Gp : -Gp;
+        sz = d.z > 0.0f ? Gp * Gp : -Gp * Gp;
         tx = tm[0];
         ty = tm[1];
         tz = tm[2];
@@ -351,61 +370,70 @@ struct GridWalk {
     }
 
     // Both tentative points of one iteration in a single walk: point A for
-    // tauA (when wantA), then point B for tauB from A.  One loop instead of
-    // two keeps the wave's trip count at the maximum over lanes of the cells
-    // both points need, not the sum of two maxima.  Points past the segment
-    // come back as tend, with the majorant of their cell in sbA / sbB.  The
-    // step is branch-free: the face crossed first is the one whose boundary
-    // equals the minimum, and the cell index moves by that axis's stride.
-    // The grid in LDS carries a border of cells that repeat the edge cells,
-    // so a step that rounding carries one cell past the grid reads the edge
-    // cell's majorant; the segment ends at the box, within rounding of the
-    // last face, so no walk goes two cells past it (the index is clamped to
-    // the padded grid all the same).  Every step raises the smallest
-    // boundary by one cell width along its axis, so the loop reaches tend
-    // within 3 (grid_n * segment length / cell width + 2) steps.
-    __device__ __forceinline__ void next2(const TraceParams& P, const float* mg, f3 d, bool wantA, float tauA,
+    // tauA (when wantA), then point B for tauB from A.  One loop for both
+    // keeps the wave's trip count at the maximum over lanes of the cells both
+    // points need, not the sum of two maxima.  Points past the segment come
+    // back as tend, with the majorant of their cell in sbA / sbB.
+    // One trip handles one cell: point A if it lies in the cell, then point B
+    // if it lies in the rest of the same cell, else the exponential variate
+    // left over and either the segment's end or a step into the next cell.
+    // The arithmetic is that of one point per trip (B's room in the cell is
+    // measured from A, with the same majorant and cell exit), so the points
+    // are the same; only trips whose cell holds both points or holds A and is
+    // then left are merged.  All outcomes are formed with selects, so lanes
+    // that take different ones run a trip's instructions once.  mg holds each
+    // padded cell's majorant s and the hardware reciprocal of s.  The face
+    // crossed first is the one whose boundary equals the minimum, and the
+    // cell index moves by that axis's signed stride.  The grid in LDS carries
+    // a border of cells that repeat the edge cells, so a step that rounding
+    // carries one cell past the grid reads the edge cell's majorant; the
+    // segment ends at the box, within rounding of the last face, so no walk
+    // goes two cells past it (the index is clamped to the padded grid all the
+    // same).  Every step raises the smallest boundary by one cell width along
+    // its axis, so the loop reaches tend within
+    // 3 (grid_n * segment length / cell width + 2) steps.
+    template <class PT>
+    __device__ __forceinline__ void next2(const PT& P, const float2* mg, bool wantA, float tauA,
                                           float tauB, float tend, float& tA, float& sbA, float& tB, float& sbB,
                                           uint32_t& steps) {
-        const int Gp = P.grid_n + 2, Gp2 = Gp * Gp, last = Gp2 * Gp - 1;
-        int phase = wantA ? 0 : 1;  // 0: looking for A, 1: looking for B, 2: done
+        const int Gp = P.grid_n + 2, last = Gp * Gp * Gp - 1;
+        bool seekA = wantA;  // still looking for A (else for B)
         float tau = wantA ? tauA : tauB;
         tA = t;
         tB = tend;
+        tend = __builtin_canonicalizef(tend);
         for (;;) {
-            const float s = mg[ci];
+            const float2 m = mg[ci];
+            const float s = m.x;
             const float tmin = fminf(fminf(tx, ty), tz);
             const float te = fminf(tmin, tend);
             const float room = s * fmaxf(te - t, 0.0f);
-            if (tau < room) {
-                t = fmaf(tau, rcp(s), t);
-                if (phase == 0) {
-                    tA = t;
-                    sbA = s;
-                    tau = tauB;
-                } else {
-                    tB = t;
-                    sbB = s;
-                }
-                ++phase;
-            } else {
-                tau -= room;
-                if (te >= tend) {
-                    if (phase == 0) tA = tend;
-                    phase = 2;
-                } else {
-                    t = te;
-                    ++steps;
-                    const bool bx = tx == tmin, by = !bx && ty == tmin, bz = !bx && !by;
-                    const int st = bx ? 1 : (by ? Gp : Gp2);
-                    const bool up = bx ? d.x > 0.0f : (by ? d.y > 0.0f : d.z > 0.0f);
-                    ci = min(max(up ? ci + st : ci - st, 0), last);
-                    tx += bx ? dx : 0.0f;
-                    ty += by ? dy : 0.0f;
-                    tz += bz ? dz : 0.0f;
-                }
-            }
-            if (phase == 2) break;
+            const float th = fmaf(tau, m.y, t);        // the current target's point (s > 0 when it lies here)
+            const bool hitA = seekA && tau < room;     // A lies in this cell
+            // B from A in the same cell, or B as the current target
+            const float tb0 = hitA ? th : t;
+            const float taub = hitA ? tauB : tau;
+            const float roomb = hitA ? s * fmaxf(te - th, 0.0f) : room;
+            const float thb = hitA ? fmaf(taub, m.y, tb0) : th;
+            const bool hitB = (hitA || !seekA) && taub < roomb;
+            const bool end = !hitB && te >= tend;        // the segment ends in this cell
+            const bool step = !hitB && !end;             // on into the next cell
+            tA = hitA ? th : ((end && seekA) ? tend : tA);
+            sbA = hitA ? s : sbA;
+            tB = hitB ? thb : tB;
+            sbB = hitB ? s : sbB;
+            t = te;
+            tau = taub - roomb;
+            seekA = seekA && !hitA;
+            steps += step ? 1u : 0u;
+            const bool bx = tx == tmin, by = !bx && ty == tmin, bz = !bx && !by;
+            // (exactly one of bx, by, bz holds: a sum of selects, not an indexed pick)
+            const int st = (bx ? sx : 0) + (by ? sy : 0) + (bz ? sz : 0);
+            ci = min(max(ci + st, 0), last);
+            tx += bx ? dx : 0.0f;
+            ty += by ? dy : 0.0f;
+            tz += bz ? dz : 0.0f;
+            if (!step) break;
         }
     }
 };

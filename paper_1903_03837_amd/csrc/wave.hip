@@ -55,8 +55,9 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     float4* lut_e = smem;
     float4* lut_s = smem + (MODE == kFrozen ? P.lut_n : 0);
     float* glds = (float*)(smem + P.lut_n);  // kGrad: dLUT [lut_n][4], dscale
-    // cell majorants after the tables above
-    float* mg = (float*)smem + 4 * P.lut_n * (MODE == kFrozen ? 2 : 1) + (MODE == kGrad ? 4 * P.lut_n + 1 : 0);
+    // cell majorants and their reciprocals after the tables above (8-byte aligned)
+    float2* mg = (float2*)((float*)smem + ((4 * P.lut_n * (MODE == kFrozen ? 2 : 1) +
+                                            (MODE == kGrad ? 4 * P.lut_n + 1 : 0) + 1) & ~1));
     const int ncell = (P.grid_n + 2) * (P.grid_n + 2) * (P.grid_n + 2);  // padded grid
     for (int e = threadIdx.x; e < P.lut_n; e += blockDim.x) {
         lut_e[e] = ((const float4*)P.lut_e)[e];
@@ -67,33 +68,26 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
         const int Gp = P.grid_n + 2, ex = e % Gp, ey = (e / Gp) % Gp, ez = e / (Gp * Gp);
         const int G1 = P.grid_n - 1;
         const int cx = min(max(ex - 1, 0), G1), cy = min(max(ey - 1, 0), G1), cz = min(max(ez - 1, 0), G1);
-        mg[e] = P.maj[(cz * P.grid_n + cy) * P.grid_n + cx];
+        const float m = P.maj[(cz * P.grid_n + cy) * P.grid_n + cx];
+        mg[e] = make_float2(m, rcp(m));
     }
     if constexpr (MODE == kGrad)
         for (int e = threadIdx.x; e < 4 * P.lut_n + 1; e += blockDim.x) glds[e] = 0.0f;
     __syncthreads();
 
     const float sigbar = *P.sigbar;
-    const uint32_t K0 = P.key0, K1 = P.key1;
     const int lane = threadIdx.x & 63;
-    const int rows = P.row_end - P.row_begin;
-    const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
-    // Each ray is split into 2^plog work items, ranges of its samples, for
-    // load balance (the rays of the last tiles would otherwise hold the grid
-    // long after most waves are done).  Adjoint: the scores add up in any
-    // order.  Forward with more than one range: each item leaves its partial
-    // sum in part_sums, and a second kernel adds the ranges in order.
-    const int plog = P.part_log2;
-    const int parts = 1 << plog;
-    const long long nlist = MODE == kGrad ? (long long)*P.ray_count * parts : 0;
+    // Each ray is split into 2^part_log2 work items, ranges of its samples,
+    // for load balance (the rays of the last tiles would otherwise hold the
+    // grid long after most waves are done).  Adjoint: the scores add up in
+    // any order.  Forward with more than one range: each item leaves its
+    // partial sum in part_sums, and a second kernel adds the ranges in order.
+    const long long nlist = MODE == kGrad ? (long long)*P.ray_count << P.part_log2 : 0;
     const long long ntiles = MODE == kGrad ? (nlist + 63) / 64
-                             : VIEWS     ? (long long)P.nviews * P.vtiles * parts
-                                         : (long long)tiles_i * tiles_j * parts;
+                             : VIEWS     ? ((long long)P.nviews * P.vtiles) << P.part_log2
+                                         : ((long long)((P.row_end - P.row_begin + 7) / 8) * ((P.N + 7) / 8))
+                                               << P.part_log2;
     const int home = blockIdx.x % kParts;
-    const float inv_spp = 1.0f / (float)P.spp;
-    const f3 O = mk3(P.O[0], P.O[1], P.O[2]);
-    const f3 env = mk3(P.env[0], P.env[1], P.env[2]);
-    const f3 bmin = mk3(P.bmin[0], P.bmin[1], P.bmin[2]), bmax = mk3(P.bmax[0], P.bmax[1], P.bmax[2]);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     // wave-uniform queue cursor: rays [cur, end) of the current tile
@@ -120,7 +114,64 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     G.c0 = G.c1 = 0.0f;
     G.dscale = 0.0f;
 
+    KTraceParams* Pk = (KTraceParams*)__builtin_amdgcn_kernarg_segment_ptr();
     for (;;) {
+        // parameters reloaded in each iteration (scalar loads; see KTraceParams)
+        asm volatile("" : "+s"(Pk));
+        const KTraceParams& P = *Pk;
+        const uint32_t K0 = P.key0, K1 = P.key1;
+        const int rows = P.row_end - P.row_begin;
+        const int tiles_i = (rows + 7) / 8, tiles_j = (P.N + 7) / 8;
+        const int plog = P.part_log2;
+        const int parts = 1 << plog;
+        const float inv_spp = 1.0f / (float)P.spp;
+        const f3 O = mk3(P.O[0], P.O[1], P.O[2]);
+        const f3 env = mk3(P.env[0], P.env[1], P.env[2]);
+        // adding a zero environment leaves a sum of +0 at +0: such sums are skipped
+        const bool env_zero = env.x == 0.0f && env.y == 0.0f && env.z == 0.0f;
+        const f3 bmin = mk3(P.bmin[0], P.bmin[1], P.bmin[2]), bmax = mk3(P.bmax[0], P.bmax[1], P.bmax[2]);
+        // ------------------------------------------------------ sample end
+        // (of the samples that ended in the previous iteration's passes)
+        if (mode == kDone) {
+            bool next = true;
+            if constexpr (MODE == kGrad) {
+                if (pass == 0) {  // replay the same sample with scores
+                    ltot = L;
+                    pass = 1;
+                    next = false;
+                } else {
+                    pass = P.srad ? 1 : 0;
+                }
+            } else {
+                acc = acc + L;
+                if (P.srad && !VIEWS) {
+                    float* o = P.srad + 3 * ((uint64_t)k * (uint32_t)P.spp + (uint32_t)s);
+                    o[0] = L.x;
+                    o[1] = L.y;
+                    o[2] = L.z;
+                }
+            }
+            if (next && ++s == s_end) {
+                if constexpr (MODE != kGrad) {
+                    if (parts == 1) {
+                        const float fs = (float)P.spp;
+                        store_texel(P.out, P.dtype, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
+                    } else {  // this range's sum, for the combining kernel
+                        const uint64_t kl = (uint64_t)k - (uint64_t)P.row_begin * (uint32_t)P.N;
+                        float* o = P.part_sums + 3 * (kl * parts + part);
+                        o[0] = acc.x;
+                        o[1] = acc.y;
+                        o[2] = acc.z;
+                    }
+                }
+                mode = kIdle;
+            } else {
+                mode = kStart;
+                b = 0;
+                blk = 0;
+            }
+        }
+
         // ------------------------------------------------------------ refill
         const uint64_t idle = __ballot(mode == kIdle);
         if (idle) {
@@ -223,7 +274,8 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         // usual.  (The adjoint's ray list leaves such rays out.)
                         if constexpr (MODE != kGrad) {
                             if (misses_box(P, O, bmin, bmax, po, d0)) {
-                                for (int s2 = s_first + 1; s2 < s_end; ++s2) acc = acc + env;
+                                if (!env_zero)
+                                    for (int s2 = s_first + 1; s2 < s_end; ++s2) acc = acc + env;
                                 cnt.samples += (uint32_t)(s_end - 1 - s_first);
                                 s = s_end - 1;
                             }
@@ -237,277 +289,251 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
             continue;
         }
 
-        // ------------------------------------------------------ one block
-        const bool vstream = mode == kVertex || mode == kShadow || mode == kShadow2;
-        const u4 r = philox(k, (uint32_t)s, ((uint32_t)b << 8) | (vstream ? kPurVertex : kPurFlight), blk, K0, K1);
-        bool stepA = mode == kFlight || mode == kShadow || mode == kShadow2;
-        bool stepB = stepA;
-        bool sample_done = false, after_shadow = false;
+        // Passes: the first one draws a block for every lane and runs the
+        // set-up of START, SCATTER and VERTEX lanes; further passes, while at
+        // least kTrackPass lanes are still tracking a segment, advance only
+        // those lanes by one block each.  A lane whose segment needs a set-up
+        // or whose sample ended waits for the next iteration, so the set-up
+        // and sample-end code runs once per iteration for all such lanes.
+        // Every lane still takes the same steps in the same order.
+        for (bool first = true;; first = false) {
+            // ------------------------------------------------------ one block
+            const bool vstream = mode == kVertex || mode == kShadow || mode == kShadow2;
+            const u4 r = philox(k, (uint32_t)s, ((uint32_t)b << 8) | (vstream ? kPurVertex : kPurFlight), blk, K0, K1);
+            bool stepA = mode == kFlight || mode == kShadow || mode == kShadow2;
+            bool stepB = stepA;
+            bool sample_done = false, after_shadow = false;
 
-        // --------------------------------------------------- segment set-up
-        // A sample's first segment (START), the segment after a scatter
-        // (SCATTER: b already advanced) and the shadow ray of a vertex
-        // (VERTEX) share one rotation (START's jitter disk, SCATTER's phase
-        // direction) and one clip against the box.
-        const bool seg = mode == kStart || mode == kScatter;
-        const bool shadow_ray = mode == kVertex && P.light_on;
-        f3 Le = mk3(0.0f, 0.0f, 0.0f);
-        float dist = 0.0f;
-        if (mode == kVertex) {
-            // next-event estimation: light sample (pair 0); phase words (pair 1) kept for the scatter
-            up0 = u01(r.z);
-            up1 = u01(r.w);
-            if (P.light_on) {
-                if (P.light_kind == 0) {
-                    om = mk3(P.ldir[0], P.ldir[1], P.ldir[2]);
-                    Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]);
-                } else {
-                    const f3 yl = mk3(P.lcorner[0], P.lcorner[1], P.lcorner[2]) +
-                                  mk3(P.le1[0], P.le1[1], P.le1[2]) * u01(r.x) +
-                                  mk3(P.le2[0], P.le2[1], P.le2[2]) * u01(r.y);
-                    const f3 v = yl - x;
-                    const float d2 = dot(v, v);
-                    const float rinv = rsq(d2);
-                    dist = d2 * rinv;
-                    om = v * rinv;
-                    const float cl = fmaxf(0.0f, -dot(mk3(P.lnrm[0], P.lnrm[1], P.lnrm[2]), om));
-                    Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * (cl * P.larea * rcp(d2));
-                }
-            } else {
-                after_shadow = true;
-            }
-        } else if (seg) {
-            // base + A (cos(2 pi u) t1 + sin(2 pi u) t2), (t1, t2) completing n
-            f3 n, base;
-            float A, ua;
-            if (mode == kStart) {
-                cnt.samples++;
-                if constexpr (MODE == kGrad) {
-                    if (P.srad) {  // the sample's total radiance, kept by the forward
-                        const float* lt = P.srad + 3 * ((uint64_t)k * (uint32_t)P.spp + (uint32_t)s);
-                        ltot = mk3(lt[0], lt[1], lt[2]);
-                    }
-                }
-                // light-field ray: origin on S (jittered); view ray: the eye
-                base = VIEWS ? po : O + po * P.R;
-                n = po;
-                A = (P.jitter && !VIEWS) ? P.jit_rad * sqrtf(u01(r.x)) : 0.0f;
-                ua = u01(r.y);
-                T = mk3(1.0f, 1.0f, 1.0f);
-                W = 1.0f;
-                L = mk3(0.0f, 0.0f, 0.0f);
-            } else {
-                const float mu = hg_mu(P.g, up0);
-                A = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
-                base = dir * mu;
-                n = dir;
-                ua = up1;
-            }
-            float sa, ca;
-            sincospif(2.0f * ua, &sa, &ca);
-            f3 t1, t2;
-            frame(n, t1, t2);
-            const f3 v = base + t1 * (A * ca) + t2 * (A * sa);
-            if (mode == kStart) {
-                x = v;
-                dir = d0;
-            } else {
-                dir = v;
-            }
-        }
-        if (seg || shadow_ray) {
-            float tn, tf;
-            const bool hit = clip_box(bmin, bmax, x, shadow_ray ? om : dir, tn, tf);
-            if (shadow_ray) {
-                const float te = hit ? (P.light_kind == 0 ? tf : fminf(dist, tf)) : 0.0f;
-                C = T * Le * (W * hg_phase(P.g, dot(dir, om)));
-                Tr = 1.0f;
-                if (sigbar > 0.0f) {
-                    t = 0.0f;
-                    tend = te;
-                    mode = kShadow;
-                    blk = 1;
-                } else {
-                    L = L + C;
-                    after_shadow = true;
-                }
-            } else if (hit && sigbar > 0.0f) {
-                // START: pair 1 is the first tentative collision (pair 0 was the
-                // jitter); SCATTER: pairs 0 and 1
-                stepA = mode == kScatter;
-                stepB = true;
-                t = tn;
-                tend = tf;
-                mode = kFlight;
-            } else {
-                L = L + T * env * W;
-                sample_done = true;
-            }
-        }
-
-        // -------------------------------------------- two tentative points
-        bool ev_end = false, ev_real = false;
-        f3 ynew = x;
-        TF te;
-        te.l0 = 0;
-        te.w = 0.0f;
-        te.a = te.a_s = 0.0f;
-        te.rgb = mk3(0.0f, 0.0f, 0.0f);
-        if (stepA || stepB) {
-            // (stepB always holds here; stepA is off for the first point of a sample)
-            const f3 sd = mode == kFlight ? dir : om;
-            GridWalk gw;
-            gw.init(P, x, sd, t);
-            float sbA = 0.0f, sbB = 0.0f, tA, tB;
-            gw.next2(P, mg, sd, stepA, neg_log1m(u01(r.x)), neg_log1m(u01(r.z)), tend, tA, sbA, tB, sbB, cnt.cells);
-            const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
-            const float rawA = sample_volume<VT>(P, yA);
-            const float rawB = sample_volume<VT>(P, yB);
-            bool more = true;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const bool use = h ? stepB : stepA;
-                if (!use || !more) continue;
-                const float th = h ? tB : tA;
-                if (th >= tend) {
-                    ev_end = true;
-                    more = false;
-                    continue;
-                }
-                const TF tf = classify<MODE>(P, lut_e, lut_s, h ? rawB : rawA);
-                const float sig_e = P.scale_e * tf.a;
-                const float sb = h ? sbB : sbA;  // majorant of the point's cell
-                t = th;
-                if (mode == kFlight) {
-                    cnt.tent++;
-                    const float sig_s = MODE == kFrozen ? P.scale_s * tf.a_s : sig_e;
-                    if (u01(h ? r.w : r.y) * sb < sig_s) {
-                        ev_real = true;
-                        more = false;
-                        ynew = h ? yB : yA;
-                        te = tf;
-                        if constexpr (MODE == kFrozen) W *= sig_e / sig_s;
-                        if constexpr (MODE == kGrad)
-                            if (pass) G.sigma(tf, P.scale_e, dot(adj, ltot - L) / sig_e);
+            if (first) {
+                // --------------------------------------------------- segment set-up
+                // A sample's first segment (START), the segment after a scatter
+                // (SCATTER: b already advanced) and the shadow ray of a vertex
+                // (VERTEX) share one rotation (START's jitter disk, SCATTER's phase
+                // direction) and one clip against the box.
+                const bool seg = mode == kStart || mode == kScatter;
+                const bool shadow_ray = mode == kVertex && P.light_on;
+                f3 Le = mk3(0.0f, 0.0f, 0.0f);
+                float dist = 0.0f;
+                if (mode == kVertex) {
+                    // next-event estimation: light sample (pair 0); phase words (pair 1) kept for the scatter
+                    up0 = u01(r.z);
+                    up1 = u01(r.w);
+                    if (P.light_on) {
+                        if (P.light_kind == 0) {
+                            om = mk3(P.ldir[0], P.ldir[1], P.ldir[2]);
+                            Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]);
+                        } else {
+                            const f3 yl = mk3(P.lcorner[0], P.lcorner[1], P.lcorner[2]) +
+                                          mk3(P.le1[0], P.le1[1], P.le1[2]) * u01(r.x) +
+                                          mk3(P.le2[0], P.le2[1], P.le2[2]) * u01(r.y);
+                            const f3 v = yl - x;
+                            const float d2 = dot(v, v);
+                            const float rinv = rsq(d2);
+                            dist = d2 * rinv;
+                            om = v * rinv;
+                            const float cl = fmaxf(0.0f, -dot(mk3(P.lnrm[0], P.lnrm[1], P.lnrm[2]), om));
+                            Le = mk3(P.lrad[0], P.lrad[1], P.lrad[2]) * (cl * P.larea * rcp(d2));
+                        }
                     } else {
-                        if constexpr (MODE == kFrozen) W *= (sb - sig_e) / (sb - sig_s);
-                        if constexpr (MODE == kGrad)
-                            if (pass) G.sigma(tf, P.scale_e, -dot(adj, ltot - L) / (sb - sig_e));
+                        after_shadow = true;
                     }
-                } else if (mode == kShadow) {
-                    cnt.shadow++;
-                    Tr *= 1.0f - sig_e * rcp(sb);
-                } else {
-                    if constexpr (MODE == kGrad) G.sigma(tf, P.scale_e, -rc / (sb - sig_e));
+                } else if (seg) {
+                    // base + A (cos(2 pi u) t1 + sin(2 pi u) t2), (t1, t2) completing n
+                    f3 n, base;
+                    float A, ua;
+                    if (mode == kStart) {
+                        cnt.samples++;
+                        if constexpr (MODE == kGrad) {
+                            if (P.srad) {  // the sample's total radiance, kept by the forward
+                                const float* lt = P.srad + 3 * ((uint64_t)k * (uint32_t)P.spp + (uint32_t)s);
+                                ltot = mk3(lt[0], lt[1], lt[2]);
+                            }
+                        }
+                        // light-field ray: origin on S (jittered); view ray: the eye
+                        base = VIEWS ? po : O + po * P.R;
+                        n = po;
+                        A = (P.jitter && !VIEWS) ? P.jit_rad * sqrtf(u01(r.x)) : 0.0f;
+                        ua = u01(r.y);
+                        T = mk3(1.0f, 1.0f, 1.0f);
+                        W = 1.0f;
+                        L = mk3(0.0f, 0.0f, 0.0f);
+                    } else {
+                        const float mu = hg_mu(P.g, up0);
+                        A = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+                        base = dir * mu;
+                        n = dir;
+                        ua = up1;
+                    }
+                    float sa, ca;
+                    sincospif(2.0f * ua, &sa, &ca);
+                    f3 t1, t2;
+                    frame(n, t1, t2);
+                    const f3 v = base + t1 * (A * ca) + t2 * (A * sa);
+                    if (mode == kStart) {
+                        x = v;
+                        dir = d0;
+                    } else {
+                        dir = v;
+                    }
                 }
+                if (seg || shadow_ray) {
+                    float tn, tf;
+                    const bool hit = clip_box(bmin, bmax, x, shadow_ray ? om : dir, tn, tf);
+                    if (shadow_ray) {
+                        const float te = hit ? (P.light_kind == 0 ? tf : fminf(dist, tf)) : 0.0f;
+                        C = T * Le * (W * hg_phase(P.g, dot(dir, om)));
+                        Tr = 1.0f;
+                        if (sigbar > 0.0f) {
+                            t = 0.0f;
+                            tend = te;
+                            mode = kShadow;
+                            blk = 1;
+                        } else {
+                            L = L + C;
+                            after_shadow = true;
+                        }
+                    } else if (hit && sigbar > 0.0f) {
+                        // START: pair 1 is the first tentative collision (pair 0 was the
+                        // jitter); SCATTER: pairs 0 and 1
+                        stepA = mode == kScatter;
+                        stepB = true;
+                        t = tn;
+                        tend = tf;
+                        mode = kFlight;
+                    } else {
+                        L = L + T * env * W;
+                        sample_done = true;
+                    }
+                }
+
             }
-            if (ev_end) {
-                if (mode == kFlight) {
-                    L = L + T * env * W;
-                    sample_done = true;
-                } else if (MODE == kGrad && mode == kShadow && pass) {
-                    // transmittance known: replay the shadow ray for its scores
-                    rc = dot(adj, C * Tr);
-                    if (rc != 0.0f) {
-                        mode = kShadow2;
-                        blk = 1;
-                        t = 0.0f;
+
+            // -------------------------------------------- two tentative points
+            bool ev_end = false, ev_real = false;
+            f3 ynew = x;
+            TF te;
+            te.l0 = 0;
+            te.w = 0.0f;
+            te.a = te.a_s = 0.0f;
+            te.rgb = mk3(0.0f, 0.0f, 0.0f);
+            if (stepA || stepB) {
+                // (stepB always holds here; stepA is off for the first point of a sample)
+                const f3 sd = mode == kFlight ? dir : om;
+                GridWalk gw;
+                gw.init(P, x, sd, t);
+                float sbA = 0.0f, sbB = 0.0f, tA, tB;
+                gw.next2(P, mg, stepA, neg_log1m(u01(r.x)), neg_log1m(u01(r.z)), tend, tA, sbA, tB, sbB, cnt.cells);
+                const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
+                const float rawA = sample_volume<VT>(P, yA);
+                const float rawB = sample_volume<VT>(P, yB);
+                bool more = true;
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bool use = h ? stepB : stepA;
+                    if (!use || !more) continue;
+                    const float th = h ? tB : tA;
+                    if (th >= tend) {
+                        ev_end = true;
+                        more = false;
+                        continue;
+                    }
+                    const TF tf = classify<MODE>(P, lut_e, lut_s, h ? rawB : rawA);
+                    const float sig_e = P.scale_e * tf.a;
+                    const float sb = h ? sbB : sbA;  // majorant of the point's cell
+                    t = th;
+                    if (mode == kFlight) {
+                        cnt.tent++;
+                        const float sig_s = MODE == kFrozen ? P.scale_s * tf.a_s : sig_e;
+                        if (u01(h ? r.w : r.y) * sb < sig_s) {
+                            ev_real = true;
+                            more = false;
+                            ynew = h ? yB : yA;
+                            te = tf;
+                            if constexpr (MODE == kFrozen) W *= sig_e / sig_s;
+                            if constexpr (MODE == kGrad)
+                                if (pass) G.sigma(tf, P.scale_e, dot(adj, ltot - L) / sig_e);
+                        } else {
+                            if constexpr (MODE == kFrozen) W *= (sb - sig_e) / (sb - sig_s);
+                            if constexpr (MODE == kGrad)
+                                if (pass) G.sigma(tf, P.scale_e, -dot(adj, ltot - L) / (sb - sig_e));
+                        }
+                    } else if (mode == kShadow) {
+                        cnt.shadow++;
+                        Tr *= 1.0f - sig_e * rcp(sb);
+                    } else {
+                        if constexpr (MODE == kGrad) G.sigma(tf, P.scale_e, -rc / (sb - sig_e));
+                    }
+                }
+                if (ev_end) {
+                    if (mode == kFlight) {
+                        L = L + T * env * W;
+                        sample_done = true;
+                    } else if (MODE == kGrad && mode == kShadow && pass) {
+                        // transmittance known: replay the shadow ray for its scores
+                        rc = dot(adj, C * Tr);
+                        if (rc != 0.0f) {
+                            mode = kShadow2;
+                            blk = 1;
+                            t = 0.0f;
+                        } else {
+                            L = L + C * Tr;
+                            after_shadow = true;
+                        }
                     } else {
                         L = L + C * Tr;
                         after_shadow = true;
                     }
-                } else {
-                    L = L + C * Tr;
-                    after_shadow = true;
-                }
-            } else if (ev_real) {
-                cnt.real++;
-                if constexpr (MODE == kGrad) {
-                    if (pass) {
-                        // albedo scores d rho_c / rho_c times the channel's later radiance
-                        const f3 after = (ltot - L) * adj;
-                        const float ra[3] = {te.rgb.x, te.rgb.y, te.rgb.z};
-                        const float af[3] = {after.x, after.y, after.z};
-#pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            if (ra[c] > 0.0f && ra[c] < 1.0f && af[c] != 0.0f) {
-                                const float f = af[c] / ra[c];
-                                atomicAdd(&glds[te.l0 * 4 + c], f * (1.0f - te.w));
-                                atomicAdd(&glds[te.l0 * 4 + 4 + c], f * te.w);
-                            }
+                } else if (ev_real) {
+                    cnt.real++;
+                    if constexpr (MODE == kGrad) {
+                        if (pass) {
+                            // albedo scores d rho_c / rho_c times the channel's later radiance
+                            const f3 after = (ltot - L) * adj;
+                            const float ra[3] = {te.rgb.x, te.rgb.y, te.rgb.z};
+                            const float af[3] = {after.x, after.y, after.z};
+    #pragma unroll
+                            for (int c = 0; c < 3; ++c)
+                                if (ra[c] > 0.0f && ra[c] < 1.0f && af[c] != 0.0f) {
+                                    const float f = af[c] / ra[c];
+                                    atomicAdd(&glds[te.l0 * 4 + c], f * (1.0f - te.w));
+                                    atomicAdd(&glds[te.l0 * 4 + 4 + c], f * te.w);
+                                }
+                        }
+                    }
+                    x = ynew;
+                    T = T * mk3(fminf(fmaxf(te.rgb.x, 0.0f), 1.0f), fminf(fmaxf(te.rgb.y, 0.0f), 1.0f),
+                                fminf(fmaxf(te.rgb.z, 0.0f), 1.0f));
+                    if (T.x == 0.0f && T.y == 0.0f && T.z == 0.0f) {
+                        sample_done = true;
+                    } else {
+                        mode = kVertex;
+                        blk = 0;
+                    }
+                } else if (++blk >= kMaxBlocks) {
+                    // stream exhausted: the segment ends absorbed / blocked
+                    if (mode == kFlight) {
+                        sample_done = true;
+                    } else {
+                        Tr = 0.0f;  // C * 0 adds nothing
+                        after_shadow = true;
                     }
                 }
-                x = ynew;
-                T = T * mk3(fminf(fmaxf(te.rgb.x, 0.0f), 1.0f), fminf(fmaxf(te.rgb.y, 0.0f), 1.0f),
-                            fminf(fmaxf(te.rgb.z, 0.0f), 1.0f));
-                if (T.x == 0.0f && T.y == 0.0f && T.z == 0.0f) {
+            }
+
+            // ------------------------------------------------ scatter direction
+            // (drawn at the start of the next iteration, from the phase words)
+            if (after_shadow) {
+                if (b == P.maxb - 1) {
                     sample_done = true;
                 } else {
-                    mode = kVertex;
+                    ++b;
                     blk = 0;
-                }
-            } else if (++blk >= kMaxBlocks) {
-                // stream exhausted: the segment ends absorbed / blocked
-                if (mode == kFlight) {
-                    sample_done = true;
-                } else {
-                    Tr = 0.0f;  // C * 0 adds nothing
-                    after_shadow = true;
+                    mode = kScatter;
                 }
             }
-        }
 
-        // ------------------------------------------------ scatter direction
-        // (drawn at the start of the next iteration, from the phase words)
-        if (after_shadow) {
-            if (b == P.maxb - 1) {
-                sample_done = true;
-            } else {
-                ++b;
-                blk = 0;
-                mode = kScatter;
-            }
-        }
-
-        // ------------------------------------------------------ sample end
-        if (sample_done) {
-            bool next = true;
-            if constexpr (MODE == kGrad) {
-                if (pass == 0) {  // replay the same sample with scores
-                    ltot = L;
-                    pass = 1;
-                    next = false;
-                } else {
-                    pass = P.srad ? 1 : 0;
-                }
-            } else {
-                acc = acc + L;
-                if (P.srad && !VIEWS) {
-                    float* o = P.srad + 3 * ((uint64_t)k * (uint32_t)P.spp + (uint32_t)s);
-                    o[0] = L.x;
-                    o[1] = L.y;
-                    o[2] = L.z;
-                }
-            }
-            if (next && ++s == s_end) {
-                if constexpr (MODE != kGrad) {
-                    if (parts == 1) {
-                        const float fs = (float)P.spp;
-                        store_texel(P.out, P.dtype, k, mk3(acc.x / fs, acc.y / fs, acc.z / fs));
-                    } else {  // this range's sum, for the combining kernel
-                        const uint64_t kl = (uint64_t)k - (uint64_t)P.row_begin * (uint32_t)P.N;
-                        float* o = P.part_sums + 3 * (kl * parts + part);
-                        o[0] = acc.x;
-                        o[1] = acc.y;
-                        o[2] = acc.z;
-                    }
-                }
-                mode = kIdle;
-            } else {
-                mode = kStart;
-                b = 0;
-                blk = 0;
-            }
+            if (sample_done) mode = kDone;
+            if (__popcll(__ballot(mode == kFlight || mode == kShadow || mode == kShadow2)) < kTrackPass) break;
         }
     }
 
@@ -662,7 +688,8 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     const size_t ncell = (size_t)(P.grid_n + 2) * (P.grid_n + 2) * (P.grid_n + 2);  // padded grid in LDS
     const size_t lds = sizeof(float4) * (size_t)P.lut_n * (MODE == kFrozen ? 2 : 1) +
-                       (MODE == kGrad ? sizeof(float) * (4 * (size_t)P.lut_n + 1) : 0) + sizeof(float) * ncell;
+                       (MODE == kGrad ? sizeof(float) * (4 * (size_t)P.lut_n + 1) : 0) + sizeof(float) +
+                       sizeof(float2) * ncell;
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
