@@ -203,9 +203,10 @@ __device__ __forceinline__ float vox(const void* v, uint32_t idx) {
 // case of three).  Its eight voxels sit at fixed offsets from the first.
 template <int VT, class PT>
 __device__ __forceinline__ float sample_volume(const PT& P, f3 y) {
-    const float gx = fminf(fmaxf(fmaf(y.x, P.ga[0], P.gb[0]), 0.0f), P.gmax[0]);
-    const float gy = fminf(fmaxf(fmaf(y.y, P.ga[1], P.gb[1]), 0.0f), P.gmax[1]);
-    const float gz = fminf(fmaxf(fmaf(y.z, P.ga[2], P.gb[2]), 0.0f), P.gmax[2]);
+    // clamp to [0, n - 1] as one median-of-three
+    const float gx = __builtin_amdgcn_fmed3f(fmaf(y.x, P.ga[0], P.gb[0]), 0.0f, P.gmax[0]);
+    const float gy = __builtin_amdgcn_fmed3f(fmaf(y.y, P.ga[1], P.gb[1]), 0.0f, P.gmax[1]);
+    const float gz = __builtin_amdgcn_fmed3f(fmaf(y.z, P.ga[2], P.gb[2]), 0.0f, P.gmax[2]);
     const int ix = min((int)gx, P.imax[0]);
     const int iy = min((int)gy, P.imax[1]);
     const int iz = min((int)gz, P.imax[2]);
@@ -230,20 +231,20 @@ struct TF {
     float w;
     float a;        // alpha of the evaluated medium
     float a_s;      // alpha of the sampling medium (kFrozen)
-    f3 rgb;         // evaluated colour, unclamped
 };
 
 // Post-classification: window, clamp, linear LUT interpolation (LUT in LDS).
+// The alpha of the point; its colour (needed at real collisions only) comes
+// from tf_rgb with the same entries and weight.
 template <int MODE, class PT>
 __device__ __forceinline__ TF classify(const PT& P, const float4* lut_e, const float4* lut_s, float raw) {
     TF t;
-    const float s = fminf(fmaxf((raw - P.vmin) * P.vscale, 0.0f), 1.0f);
+    const float s = __builtin_amdgcn_fmed3f((raw - P.vmin) * P.vscale, 0.0f, 1.0f);
     const float u = s * P.lut_last;
     t.l0 = min((int)u, P.lut_n - 2);
     t.w = u - (float)t.l0;
-    const float4 A = lut_e[t.l0], B = lut_e[t.l0 + 1];
-    t.a = fmaf(t.w, B.w - A.w, A.w);
-    t.rgb = mk3(fmaf(t.w, B.x - A.x, A.x), fmaf(t.w, B.y - A.y, A.y), fmaf(t.w, B.z - A.z, A.z));
+    const float Aw = lut_e[t.l0].w, Bw = lut_e[t.l0 + 1].w;
+    t.a = fmaf(t.w, Bw - Aw, Aw);
     if constexpr (MODE == kFrozen) {
         const float4 C = lut_s[t.l0], D = lut_s[t.l0 + 1];
         t.a_s = fmaf(t.w, D.w - C.w, C.w);
@@ -253,13 +254,24 @@ __device__ __forceinline__ TF classify(const PT& P, const float4* lut_e, const f
     return t;
 }
 
+// Evaluated colour (unclamped) of a classified point.
+__device__ __forceinline__ f3 tf_rgb(const float4* lut_e, const TF& t) {
+    const float4 A = lut_e[t.l0], B = lut_e[t.l0 + 1];
+    return mk3(fmaf(t.w, B.x - A.x, A.x), fmaf(t.w, B.y - A.y, A.y), fmaf(t.w, B.z - A.z, A.z));
+}
+
 // ---------------------------------------------------------------------------
 // Geometry
 // ---------------------------------------------------------------------------
-// [tn, tf) of o + t d, t >= 0, inside the box; false when empty.
-__device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, float& tn, float& tf) {
+// Hardware reciprocals of a direction's components (used by the clip and by
+// the majorant-grid walk of the same segment).
+__device__ __forceinline__ f3 rcp3(f3 d) { return mk3(rcp(d.x), rcp(d.y), rcp(d.z)); }
+
+// [tn, tf) of o + t d, t >= 0, inside the box; false when empty.  id: the
+// reciprocals of d's components (rcp3).
+__device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, f3 id, float& tn, float& tf) {
     float t0 = 0.0f, t1 = 3.402823466e38f;
-    const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+    const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z}, ii[3] = {id.x, id.y, id.z};
     const float lo[3] = {bmin.x, bmin.y, bmin.z}, hi[3] = {bmax.x, bmax.y, bmax.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -267,7 +279,7 @@ __device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, float& tn
             if (oo[a] < lo[a] || oo[a] > hi[a]) return false;
             continue;
         }
-        const float inv = rcp(dd[a]);
+        const float inv = ii[a];
         float ta = (lo[a] - oo[a]) * inv, tb = (hi[a] - oo[a]) * inv;
         if (ta > tb) {
             const float t = ta;
@@ -280,6 +292,10 @@ __device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, float& tn
     tn = t0;
     tf = t1;
     return t0 < t1;
+}
+
+__device__ __forceinline__ bool clip_box(f3 bmin, f3 bmax, f3 o, f3 d, float& tn, float& tf) {
+    return clip_box(bmin, bmax, o, d, rcp3(d), tn, tf);
 }
 
 // True when the light-field ray from SF origin po (unit sphere) along d0
@@ -335,11 +351,13 @@ struct GridWalk {
     int ci;          // cell index in the padded grid (one border cell per side)
     int sx, sy, sz;  // signed index steps along x, y, z (by the sign of d)
 
+    // id: the reciprocals of d's components (rcp3)
     template <class PT>
-    __device__ __forceinline__ void init(const PT& P, f3 x, f3 d, float t0) {
+    __device__ __forceinline__ void init(const PT& P, f3 x, f3 d, f3 id, float t0) {
         const int G = P.grid_n;
         const f3 p = fma3(d, t0, x);
         const float pp[3] = {p.x, p.y, p.z}, dd[3] = {d.x, d.y, d.z}, xx[3] = {x.x, x.y, x.z};
+        const float ii[3] = {id.x, id.y, id.z};
         int c[3];
         float tm[3], dl[3];
 #pragma unroll
@@ -349,7 +367,7 @@ struct GridWalk {
                 tm[a] = 3.402823466e38f;
                 dl[a] = 0.0f;
             } else {
-                const float inv = rcp(dd[a]);
+                const float inv = ii[a];
                 const float plane = fmaf((float)(c[a] + (dd[a] > 0.0f ? 1 : 0)), P.gcw[a], P.bmin[a]);
                 tm[a] = (plane - xx[a]) * inv;
                 dl[a] = P.gcw[a] * fabsf(inv);

@@ -103,6 +103,7 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
     int part = 0;       // its range index
     f3 po = mk3(0, 0, 0), d0 = po, acc = po, x = po, dir = po, T = po, L = po, om = po, C = po;
     float W = 1.0f, t = 0.0f, tend = 0.0f, Tr = 1.0f, up0 = 0.0f, up1 = 0.0f;
+    f3 isd = po;  // reciprocals of the current segment's direction (dir or om)
     Counters cnt = {0, 0, 0, 0, 0};
     // adjoint state: texel adjoint / spp, pass A radiance, pass, NEE score weight
     f3 adj = po, ltot = po;
@@ -378,7 +379,9 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                 }
                 if (seg || shadow_ray) {
                     float tn, tf;
-                    const bool hit = clip_box(bmin, bmax, x, shadow_ray ? om : dir, tn, tf);
+                    const f3 cd = shadow_ray ? om : dir;
+                    isd = rcp3(cd);  // kept for the grid walks of this segment
+                    const bool hit = clip_box(bmin, bmax, x, cd, isd, tn, tf);
                     if (shadow_ray) {
                         const float te = hit ? (P.light_kind == 0 ? tf : fminf(dist, tf)) : 0.0f;
                         C = T * Le * (W * hg_phase(P.g, dot(dir, om)));
@@ -415,19 +418,18 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
             te.l0 = 0;
             te.w = 0.0f;
             te.a = te.a_s = 0.0f;
-            te.rgb = mk3(0.0f, 0.0f, 0.0f);
             if (stepA || stepB) {
                 // (stepB always holds here; stepA is off for the first point of a sample)
                 const f3 sd = mode == kFlight ? dir : om;
                 GridWalk gw;
-                gw.init(P, x, sd, t);
+                gw.init(P, x, sd, isd, t);
                 float sbA = 0.0f, sbB = 0.0f, tA, tB;
                 gw.next2(P, mg, stepA, neg_log1m(u01(r.x)), neg_log1m(u01(r.z)), tend, tA, sbA, tB, sbB, cnt.cells);
                 const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
                 const float rawA = sample_volume<VT>(P, yA);
                 const float rawB = sample_volume<VT>(P, yB);
                 bool more = true;
-    #pragma unroll
+#pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const bool use = h ? stepB : stepA;
                     if (!use || !more) continue;
@@ -485,13 +487,14 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                     }
                 } else if (ev_real) {
                     cnt.real++;
+                    const f3 rgb = tf_rgb(lut_e, te);
                     if constexpr (MODE == kGrad) {
                         if (pass) {
                             // albedo scores d rho_c / rho_c times the channel's later radiance
                             const f3 after = (ltot - L) * adj;
-                            const float ra[3] = {te.rgb.x, te.rgb.y, te.rgb.z};
+                            const float ra[3] = {rgb.x, rgb.y, rgb.z};
                             const float af[3] = {after.x, after.y, after.z};
-    #pragma unroll
+#pragma unroll
                             for (int c = 0; c < 3; ++c)
                                 if (ra[c] > 0.0f && ra[c] < 1.0f && af[c] != 0.0f) {
                                     const float f = af[c] / ra[c];
@@ -501,8 +504,8 @@ __global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
                         }
                     }
                     x = ynew;
-                    T = T * mk3(fminf(fmaxf(te.rgb.x, 0.0f), 1.0f), fminf(fmaxf(te.rgb.y, 0.0f), 1.0f),
-                                fminf(fmaxf(te.rgb.z, 0.0f), 1.0f));
+                    T = T * mk3(__builtin_amdgcn_fmed3f(rgb.x, 0.0f, 1.0f), __builtin_amdgcn_fmed3f(rgb.y, 0.0f, 1.0f),
+                                __builtin_amdgcn_fmed3f(rgb.z, 0.0f, 1.0f));
                     if (T.x == 0.0f && T.y == 0.0f && T.z == 0.0f) {
                         sample_done = true;
                     } else {
