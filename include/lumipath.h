@@ -213,7 +213,8 @@ int lf_generate(const lf_volume* vol, const lf_medium* eval, const lf_medium* sa
  *   nn_out: NULL or int32 [n_views][H][W][2], nearest (i, j), -1 on a miss.
  *   cams: host array of n_views cameras, each eye outside S.
  *   ws / ws_bytes: workspace for the point tables of both SF sets (16 bytes
- *   per point, filled by the call); ws == NULL only sets *ws_bytes. */
+ *   per point) and their lattice bases per zone (768 bytes per set), filled
+ *   by the call; ws == NULL only sets *ws_bytes. */
 int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const lf_camera* cams, int32_t n_views,
               int32_t W, int32_t H, int32_t K, int32_t mode, float* img, float* d_lf, int32_t* nn_out, void* ws,
               size_t* ws_bytes, void* stream);
@@ -221,9 +222,10 @@ int lf_lookup(const void* lf, int32_t dtype, const lf_gen_params* params, const 
 /* lf_lookup without a workspace, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Arguments, results and errors as for lf_lookup, minus
- * ws / ws_bytes: the point tables of both SF sets live in a fixed 2 MiB
- * device array of the library (room for 2 x 65536 points, so every valid
- * M, N fits; larger tables would be rejected with LF_E_RANGE), which each
+ * ws / ws_bytes: the point tables and zone bases of both SF sets live in a
+ * fixed device array of the library of 2 MiB + 1.5 KiB (room for 2 x 65536
+ * points, so every valid M, N fits; larger tables would be rejected with
+ * LF_E_RANGE), which each
  * device holds from its first call until the process ends.  The first call
  * on a device looks up that array's address with the device current; the
  * call allocates nothing.  `stream` must belong to the current device

@@ -673,9 +673,10 @@ static int run_lookup(const void* lf, int32_t dtype, const lf_gen_params* params
     if (mode != LF_LOOKUP_ADJOINT && !lf) return fail(LF_E_ARG, "lf is NULL");
     if (mode != LF_LOOKUP_FORWARD && !d_lf) return fail(LF_E_ARG, "d_lf is NULL");
     if (mode == 2 && !target) return fail(LF_E_ARG, "target is NULL");
-    // workspace: the point tables of both SF sets
+    // workspace: the point tables of both SF sets, then their zone bases
     const size_t tab_o_bytes = align256(16 * (size_t)params->M);
-    const size_t need = tab_o_bytes + align256(16 * (size_t)params->N);
+    const size_t tab_d_bytes = align256(16 * (size_t)params->N);
+    const size_t need = tab_o_bytes + tab_d_bytes + 2 * lp::kZoneTableBytes;
     int rw = check_workspace(ws, ws_bytes, need);
     if (rw == 1) {
         *ws_bytes = need;
@@ -705,6 +706,8 @@ static int run_lookup(const void* lf, int32_t dtype, const lf_gen_params* params
     L.nn = mode == LF_LOOKUP_FORWARD ? nn_out : nullptr;
     L.tab_o = (const float4*)ws;
     L.tab_d = (const float4*)((char*)ws + tab_o_bytes);
+    L.zone_o = (const lp::SfZone*)((char*)ws + tab_o_bytes + tab_d_bytes);
+    L.zone_d = (const lp::SfZone*)((char*)ws + tab_o_bytes + tab_d_bytes + lp::kZoneTableBytes);
     // per-view geometry in double, rounded once to float
     std::vector<lp::ViewGeom> geo((size_t)n_views);
     for (int v = 0; v < n_views; ++v) {
@@ -777,7 +780,7 @@ int lf_lookup_static(const void* lf, int32_t dtype, const lf_gen_params* params,
     if (mode != LF_LOOKUP_FORWARD && mode != LF_LOOKUP_ADJOINT) return fail(LF_E_ARG, "unknown mode %d", mode);
     int r;
     if ((r = check_params(params, false))) return r;
-    const size_t need = align256(16 * (size_t)params->M) + align256(16 * (size_t)params->N);
+    const size_t need = align256(16 * (size_t)params->M) + align256(16 * (size_t)params->N) + 2 * lp::kZoneTableBytes;
     if (need > lp::kLookupScratchBytes)
         return fail(LF_E_RANGE, "lf_lookup_static: the point tables need %zu bytes, above its fixed scratch of %zu",
                     need, lp::kLookupScratchBytes);

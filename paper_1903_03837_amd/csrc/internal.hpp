@@ -33,6 +33,8 @@ struct LookupParams {
     int32_t* nn;
     const float4* tab_o;    // SF point tables (workspace), float4 per point
     const float4* tab_d;
+    const SfZone* zone_o;   // zone bases of both sets (workspace), kZones each
+    const SfZone* zone_d;
     ViewGeom v[kMaxViewsPerLaunch];
 };
 
@@ -93,10 +95,13 @@ hipError_t launch_active_rays(const TraceParams& P, hipStream_t s);
 hipError_t launch_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_lookup(const LookupParams& P, int mode, hipStream_t s);
 // Fixed device scratch of lf_lookup_static (lookup.hip): room for the point
-// tables of two SF sets of up to 65536 points each.  lookup_scratch() gives
+// tables and zone bases of two SF sets of up to 65536 points each.  lookup_scratch() gives
 // its address on device `dev`, which must be the current device on the first
 // call for that device.
-constexpr size_t kLookupScratchPoints = 2 * 65536;
+// (each zone table: kZones bases of 32 bytes, 768 bytes with alignment)
+constexpr size_t kZoneTableBytes = 768;
+static_assert(sizeof(SfZone) * kZones <= kZoneTableBytes, "zone table");
+constexpr size_t kLookupScratchPoints = 2 * 65536 + 2 * kZoneTableBytes / 16;
 constexpr size_t kLookupScratchBytes = kLookupScratchPoints * 16;
 constexpr int kMaxScratchDevices = 64;
 hipError_t lookup_scratch(int dev, void** ptr);

@@ -22,6 +22,24 @@
 
 namespace lp {
 
+// Texel at byte address p of a light field of type DT.
+template <int DT>
+__device__ __forceinline__ f3 load_texel_at(const char* p) {
+    if constexpr (DT == 0) {
+        const float* q = (const float*)p;
+        return mk3(q[0], q[1], q[2]);
+    } else if constexpr (DT == 1) {
+        const __half* q = (const __half*)p;
+        return mk3(__half2float(q[0]), __half2float(q[1]), __half2float(q[2]));
+    } else {
+        const uint16_t* q = (const uint16_t*)p;
+        return mk3(__uint_as_float((uint32_t)q[0] << 16), __uint_as_float((uint32_t)q[1] << 16),
+                   __uint_as_float((uint32_t)q[2] << 16));
+    }
+}
+template <int DT>
+constexpr int texel_bytes() { return DT == 0 ? 12 : 6; }
+
 template <int DT>
 __device__ __forceinline__ f3 load_texel(const void* lf, uint64_t t) {
     if constexpr (DT == 0) {
@@ -275,6 +293,8 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
             const f3 qo = normalize(fma3(d, -b - sq, oc));
             const f3 qd = normalize(fma3(d, -b + sq, oc));
             float da[KMAX], db[KMAX];
+            // (one search after the other: the scatter's registers leave no room
+            // for both searches' candidate sets at once)
             {
                 Cand9 C;
                 sf_nearest(P.M, P.invM, SfTable{P.tab_o}, qo, sf_zone(P.M, qo.z), C);
@@ -385,6 +405,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int v = blockIdx.z;
+    // zone bases of both sets, in LDS
+    __shared__ SfZone zb[2 * kZones];
+    if (threadIdx.x < 2 * kZones) zb[threadIdx.x] = threadIdx.x < kZones ? P.zone_o[threadIdx.x] : P.zone_d[threadIdx.x - kZones];
+    __syncthreads();
     if (px >= P.W || py >= P.H) return;
     const ViewGeom& G = P.v[v];
     const uint64_t pix = ((uint64_t)(P.view0 + v) * P.H + py) * P.W + px;
@@ -393,7 +417,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     const f3 fwd = mk3(G.fwd[0], G.fwd[1], G.fwd[2]);
     const f3 rt = mk3(G.right[0], G.right[1], G.right[2]);
     const f3 up = mk3(G.up[0], G.up[1], G.up[2]);
-    const f3 d = normalize(fwd + rt * ndx + up * ndy);
+    // (squared lengths: the view ray's is at least 1, the hits' about R^2, and
+    // disc exceeds 1e-6 R^2, so the short correctly rounded square root applies)
+    const f3 d = normalize_big(fwd + rt * ndx + up * ndy);
     const f3 oc = mk3(G.oc[0], G.oc[1], G.oc[2]);
     const float b = dot(d, oc);
     const float disc = b * b - G.c;
@@ -408,23 +434,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
         }
         return;
     }
-    const float sq = sqrtf(disc);
-    const f3 qo = normalize(fma3(d, -b - sq, oc));
-    const f3 qd = normalize(fma3(d, -b + sq, oc));
+    const float sq = sqrt_big(disc);
+    const f3 qo = normalize_big(fma3(d, -b - sq, oc));
+    const f3 qd = normalize_big(fma3(d, -b + sq, oc));
 
     int ia[KMAX], jb[KMAX];
     float da[KMAX], db[KMAX];
     {
-        Cand9 C;
-        const int k = sf_zone(P.M, qo.z);
-        sf_nearest(P.M, P.invM, SfTable{P.tab_o}, qo, k, C);
-        select_k<KMAX>(C, P.K, ia, da);
-    }
-    {
-        Cand9 C;
-        const int k = sf_zone(P.N, qd.z);
-        sf_nearest(P.N, P.invN, SfTable{P.tab_d}, qd, k, C);
-        select_k<KMAX>(C, P.K, jb, db);
+        Cand9 Co, Cd;
+        const int ko = sf_zone(P.M, qo.z), kd = sf_zone(P.N, qd.z);
+        sf_nearest_pair(P.M, P.invM, SfTable{P.tab_o}, qo, ko, zb[ko], Co, P.N, P.invN, SfTable{P.tab_d}, qd, kd,
+                        zb[kZones + kd], Cd);
+        select_k<KMAX>(Co, P.K, ia, da);
+        select_k<KMAX>(Cd, P.K, jb, db);
     }
     if (P.nn) {
         P.nn[2 * pix] = ia[0];
@@ -447,8 +469,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     float wa[KMAX], wb[KMAX];
 #pragma unroll
     for (int a = 0; a < KMAX; ++a) {
-        wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight(da[a], P.inv_rM) : 0.0f;
-        wb[a] = jb[a] >= 0 ? tent_weight(db[a], P.inv_rN) : 0.0f;
+        wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight_big(da[a], P.inv_rM) : 0.0f;
+        wb[a] = jb[a] >= 0 ? tent_weight_big(db[a], P.inv_rN) : 0.0f;
     }
     float wsum = 0.0f;
 #pragma unroll
@@ -462,6 +484,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
         f3 acc = mk3(0.0f, 0.0f, 0.0f);
         if (wsum > 0.0f) {
             const float inv = 1.0f / wsum;
+            // unconditional, in-range gathers so all KMAX^2 loads issue together;
+            // a texel's address is its origin row's base plus its column offset
 #pragma unroll
             for (int a = 0; a < KMAX; ++a)
 #pragma unroll
@@ -513,9 +537,19 @@ hipError_t launch_sf_table(int n, float inv_n, float4* out, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Zone bases of both SF sets (sf_zone_basis for k = 0 .. kZones - 1).
+__global__ void sf_zone_kernel(float inv_m, float inv_n, SfZone* zo, SfZone* zd) {
+    const int k = threadIdx.x;
+    if (k < kZones) zo[k] = sf_zone_basis(k, inv_m);
+    else if (k < 2 * kZones) zd[k - kZones] = sf_zone_basis(k - kZones, inv_n);
+}
+
 hipError_t launch_sf_tables(const LookupParams& P, hipStream_t s) {
     hipError_t e = launch_sf_table(P.M, P.invM, (float4*)P.tab_o, s);
-    return e == hipSuccess ? launch_sf_table(P.N, P.invN, (float4*)P.tab_d, s) : e;
+    if (e == hipSuccess) e = launch_sf_table(P.N, P.invN, (float4*)P.tab_d, s);
+    if (e != hipSuccess) return e;
+    sf_zone_kernel<<<1, 64, 0, s>>>(P.invM, P.invN, (SfZone*)P.zone_o, (SfZone*)P.zone_d);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

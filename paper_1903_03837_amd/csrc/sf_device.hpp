@@ -40,6 +40,21 @@ __device__ __forceinline__ f3 cross(f3 a, f3 b) {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 __device__ __forceinline__ f3 normalize(f3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+
+// Correctly rounded square root of x = +0 or finite x >= 2^-96: the hardware
+// square root (within 1 ulp), then its lower or upper neighbour by the sign
+// of the fma residual.  For such x this is the value sqrtf gives (sqrtf also
+// rescales inputs below 2^-96 and passes special values through, which costs
+// another seven instructions).
+__device__ __forceinline__ float sqrt_big(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float lo = __uint_as_float(__float_as_uint(s) - 1u), hi = __uint_as_float(__float_as_uint(s) + 1u);
+    float r = fmaf(-lo, s, x) <= 0.0f ? lo : s;
+    r = fmaf(-hi, s, x) > 0.0f ? hi : r;
+    return r;
+}
+// normalize() of a vector whose squared length is at least 2^-96.
+__device__ __forceinline__ f3 normalize_big(f3 a) { return a * (1.0f / sqrt_big(dot(a, a))); }
 __device__ __forceinline__ f3 fma3(f3 a, float s, f3 b) {  // a * s + b
     return {fmaf(a.x, s, b.x), fmaf(a.y, s, b.y), fmaf(a.z, s, b.z)};
 }
@@ -133,13 +148,31 @@ __device__ __forceinline__ bool closer(float da, int ia, float db, int ib) {
     return da < db || (da == db && ia < ib);
 }
 
-// Nearest point by the lattice-cell corners (no descent yet).
-template <class Pts>
-__device__ __forceinline__ int sf_cell_nearest(int n, float inv_n, const Pts& pts, f3 q, int k, float& best_d2) {
+// Lattice basis of zone k of an SF set of n points in (azimuth, height): the
+// index steps F(k) and F(k+1) move by (b00, b10) and (b01, b11); inv_det is
+// the inverse of the basis determinant.
+struct SfZone {
+    float b00, b01, b10, b11, inv_det, pad0, pad1, pad2;
+};
+constexpr int kZones = 21;  // k = 0 .. 20 (zones 0 and 1 are never used)
+__device__ __forceinline__ SfZone sf_zone_basis(int k, float inv_n) {
+    SfZone Z;
     const int F0 = fib(k), F1 = fib(k + 1);
-    const float b00 = sf_dphi(F0), b01 = sf_dphi(F1);
-    const float b10 = -2.0f * (float)F0 * inv_n, b11 = -2.0f * (float)F1 * inv_n;
-    const float inv_det = 1.0f / (b00 * b11 - b01 * b10);
+    Z.b00 = sf_dphi(F0);
+    Z.b01 = sf_dphi(F1);
+    Z.b10 = -2.0f * (float)F0 * inv_n;
+    Z.b11 = -2.0f * (float)F1 * inv_n;
+    Z.inv_det = 1.0f / (Z.b00 * Z.b11 - Z.b01 * Z.b10);
+    Z.pad0 = Z.pad1 = Z.pad2 = 0.0f;
+    return Z;
+}
+
+// Nearest point by the lattice-cell corners (no descent yet), the zone's
+// basis given.
+template <class Pts>
+__device__ __forceinline__ int sf_cell_nearest_z(int n, float inv_n, const Pts& pts, f3 q, const SfZone& Z,
+                                                 float& best_d2) {
+    const float b00 = Z.b00, b01 = Z.b01, b10 = Z.b10, b11 = Z.b11, inv_det = Z.inv_det;
     const float z0 = 1.0f - inv_n;
     const float v0 = atan2f(q.y, q.x), v1 = q.z - z0;
     const float c0 = floorf((b11 * v0 - b01 * v1) * inv_det);
@@ -162,6 +195,12 @@ __device__ __forceinline__ int sf_cell_nearest(int n, float inv_n, const Pts& pt
     return best;
 }
 
+// Nearest point by the lattice-cell corners (no descent yet).
+template <class Pts>
+__device__ __forceinline__ int sf_cell_nearest(int n, float inv_n, const Pts& pts, f3 q, int k, float& best_d2) {
+    return sf_cell_nearest_z(n, inv_n, pts, q, sf_zone_basis(k, inv_n), best_d2);
+}
+
 // Candidate set of a centre index: c + {0, +-F(k-1), +-F(k), +-F(k+1),
 // +-F(k+2)} inside [0, n), duplicates (zone 2: F(1) = F(2)) replaced by
 // invalid entries (d2 = +inf, distinct large keys).
@@ -182,7 +221,7 @@ __device__ __forceinline__ void sf_candidates(int n, const Pts& pts, f3 q, int k
         }
         const int ci = c + off;
         const bool dup = (t == 1 || t == 2) && f1 == f2;
-        const bool ok = ci >= 0 && ci < n && !dup;
+        const bool ok = (unsigned)ci < (unsigned)n && !dup;
         C.idx[t] = ok ? ci : 0x7fffff00 + t;
         C.d2[t] = ok ? dist2(q, pts(ci)) : 3.402823466e38f;
     }
@@ -208,6 +247,50 @@ __device__ __forceinline__ int sf_nearest(int n, float inv_n, const Pts& pts, f3
         c = best;
     }
     return c;
+}
+
+template <class Pts>
+__device__ __forceinline__ int cand_best(const Cand9& C) {
+    int best = C.idx[0];
+    float bdd = C.d2[0];
+#pragma unroll
+    for (int t = 1; t < 9; ++t)
+        if (closer(C.d2[t], C.idx[t], bdd, best)) {
+            bdd = C.d2[t];
+            best = C.idx[t];
+        }
+    return best;
+}
+
+// sf_nearest for two independent queries (the front and the back hit of a
+// view ray), each with its zone's basis (sf_zone_basis): the lattice corners of both, then the first candidate sets of
+// both, in straight-line code, so that the point-table loads of the two
+// searches are in flight together; the rare further descent steps follow
+// per query.  Each query takes the same steps as in sf_nearest (the same
+// centres and candidate sets, and the same cap of 16 sets), so C1 and C2
+// are the sets sf_nearest leaves.
+template <class Pts>
+__device__ __forceinline__ void sf_nearest_pair(int n1, float inv1, const Pts& p1, f3 q1, int k1, const SfZone& Z1,
+                                                Cand9& C1, int n2, float inv2, const Pts& p2, f3 q2, int k2,
+                                                const SfZone& Z2, Cand9& C2) {
+    float bd1, bd2;
+    int c1 = sf_cell_nearest_z(n1, inv1, p1, q1, Z1, bd1);
+    int c2 = sf_cell_nearest_z(n2, inv2, p2, q2, Z2, bd2);
+    sf_candidates(n1, p1, q1, k1, c1, C1);
+    sf_candidates(n2, p2, q2, k2, c2, C2);
+    int b1 = cand_best<Pts>(C1), b2 = cand_best<Pts>(C2);
+    for (int it = 1; b1 != c1; ++it) {
+        c1 = b1;
+        if (it == 16) break;
+        sf_candidates(n1, p1, q1, k1, c1, C1);
+        b1 = cand_best<Pts>(C1);
+    }
+    for (int it = 1; b2 != c2; ++it) {
+        c2 = b2;
+        if (it == 16) break;
+        sf_candidates(n2, p2, q2, k2, c2, C2);
+        b2 = cand_best<Pts>(C2);
+    }
 }
 
 // Comparators (a, b), a < b, that leave the five smallest of nine keys in
@@ -270,6 +353,11 @@ __device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, flo
 // kernel of size R sqrt(4 pi / N), with R scaled out).
 __device__ __forceinline__ float tent_weight(float d2, float inv_r) {
     return fmaxf(0.0f, 1.0f - sqrtf(d2) * inv_r);
+}
+// The same weight with the short square root: a d2 below 2^-96 gives weight 1
+// with either square root (sqrt(d2) * inv_r < 2^-41 for n <= 65535).
+__device__ __forceinline__ float tent_weight_big(float d2, float inv_r) {
+    return fmaxf(0.0f, 1.0f - sqrt_big(d2) * inv_r);
 }
 
 }  // namespace lp

@@ -216,7 +216,8 @@ def test_lookup_workspace_query(lp):
     sz = C.c_size_t(0)
     r = lp.library().lf_lookup(FAKE, 0, C.byref(prm), arr, 1, 8, 8, 5, 0, FAKE, None, None, None, C.byref(sz),
                                None)
-    assert r == LF_OK and sz.value == 2 * 1024  # the point tables of 64 + 64 SF points, 16 B each
+    # the point tables of 64 + 64 SF points (16 B each), then the zone bases of both sets (768 B each)
+    assert r == LF_OK and sz.value == 2 * 1024 + 2 * 768
     sz = C.c_size_t(100)
     r = lp.library().lf_lookup(FAKE, 0, C.byref(prm), arr, 1, 8, 8, 5, 0, FAKE, None, None, FAKE, C.byref(sz),
                                None)
