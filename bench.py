@@ -399,7 +399,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the timed step (for profiler runs)")
+                    help="only the timed step and its work counts (for profiler runs)")
     ap.add_argument("--subset-frac", type=float, default=0.01,
                     help="share of the rays in the seeded subset the oracle traces")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -467,13 +467,6 @@ def main():
     gen_s = legs["generate"] / 1e3
     khash = kernel_source_hash()
 
-    if args.no_extras:
-        print(json.dumps({"metric": "LF path samples/s + %HBM roofline; FP16 vs FP32 err; adjoint/forward time",
-                          "value": M * N * spp / (ms_per_step / 1e3), "unit": "path samples/s", "n_gpus": 1,
-                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-                          "legs_ms": legs, "kernel_hash": khash}), flush=True)
-        return
-
     # work counts of one launch (deterministic for the fixed stream)
     stats = torch.zeros(5, dtype=torch.int64, device=dev)
     lp.generate(vol, med, light, prm, out=lf, stats=stats)
@@ -490,7 +483,7 @@ def main():
 
     # the same field stored as FP16 and BF16
     low = {}
-    for name in ("f16", "bf16"):
+    for name in (() if args.no_extras else ("f16", "bf16")):
         t = lp.generate(vol, med, light, prm, dtype=name)
         ms_low = timed_ms(lambda: lp.generate(vol, med, light, prm, dtype=name, out=t), 1, stream)
         low[name] = (t, ms_low)
@@ -562,6 +555,9 @@ def main():
     }
     del img
     torch.cuda.empty_cache()
+    if args.no_extras:
+        print(json.dumps(out), flush=True)
+        return
 
     if not args.no_cpu_baseline:
         # the oracle on the seeded ray subset: the CPU baseline and the error
