@@ -443,10 +443,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     {
         Cand9 Co, Cd;
         const int ko = sf_zone(P.M, qo.z), kd = sf_zone(P.N, qd.z);
+        bool conv_o, conv_d;
         sf_nearest_pair(P.M, P.invM, SfTable{P.tab_o}, qo, ko, zb[ko], Co, P.N, P.invN, SfTable{P.tab_d}, qd, kd,
-                        zb[kZones + kd], Cd);
-        select_k<KMAX>(Co, P.K, ia, da);
-        select_k<KMAX>(Cd, P.K, jb, db);
+                        zb[kZones + kd], Cd, conv_o, conv_d);
+        select_k<KMAX>(Co, P.K, ia, da, conv_o);
+        select_k<KMAX>(Cd, P.K, jb, db, conv_d);
     }
     if (P.nn) {
         P.nn[2 * pix] = ia[0];

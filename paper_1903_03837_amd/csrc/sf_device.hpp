@@ -268,26 +268,34 @@ __device__ __forceinline__ int cand_best(const Cand9& C) {
 // searches are in flight together; the rare further descent steps follow
 // per query.  Each query takes the same steps as in sf_nearest (the same
 // centres and candidate sets, and the same cap of 16 sets), so C1 and C2
-// are the sets sf_nearest leaves.
+// are the sets sf_nearest leaves; conv1 / conv2 tell whether each set is
+// centred on its own nearest candidate (always, unless the cap was reached).
 template <class Pts>
 __device__ __forceinline__ void sf_nearest_pair(int n1, float inv1, const Pts& p1, f3 q1, int k1, const SfZone& Z1,
                                                 Cand9& C1, int n2, float inv2, const Pts& p2, f3 q2, int k2,
-                                                const SfZone& Z2, Cand9& C2) {
+                                                const SfZone& Z2, Cand9& C2, bool& conv1, bool& conv2) {
     float bd1, bd2;
     int c1 = sf_cell_nearest_z(n1, inv1, p1, q1, Z1, bd1);
     int c2 = sf_cell_nearest_z(n2, inv2, p2, q2, Z2, bd2);
     sf_candidates(n1, p1, q1, k1, c1, C1);
     sf_candidates(n2, p2, q2, k2, c2, C2);
     int b1 = cand_best<Pts>(C1), b2 = cand_best<Pts>(C2);
+    conv1 = conv2 = true;  // the final set is centred on its own nearest candidate
     for (int it = 1; b1 != c1; ++it) {
         c1 = b1;
-        if (it == 16) break;
+        if (it == 16) {
+            conv1 = false;
+            break;
+        }
         sf_candidates(n1, p1, q1, k1, c1, C1);
         b1 = cand_best<Pts>(C1);
     }
     for (int it = 1; b2 != c2; ++it) {
         c2 = b2;
-        if (it == 16) break;
+        if (it == 16) {
+            conv2 = false;
+            break;
+        }
         sf_candidates(n2, p2, q2, k2, c2, C2);
         b2 = cand_best<Pts>(C2);
     }
@@ -303,28 +311,54 @@ __device__ constexpr int kSel5of9Net[kSel5of9][2] = {
     {0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5},
     {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {0, 8}, {4, 8}, {2, 4}, {1, 2}, {3, 4}};
 
+// Comparators (a, b) over eight keys that leave the four smallest in positions
+// 0..3 in order: Batcher's odd-even merge sort of 8 inputs, pruned of every
+// comparator the first four outputs do not need (18 of 19; a host test checks
+// all 256 inputs of zeros and ones).  When the descent has converged, the
+// centre (candidate 0) is the unique smallest key, and the five nearest are
+// the centre followed by the four smallest of the other eight.
+constexpr int kSel4of8 = 18;
+__device__ constexpr int kSel4of8Net[kSel4of8][2] = {
+    {0, 1}, {2, 3}, {0, 2}, {1, 3}, {1, 2}, {4, 5}, {6, 7}, {4, 6}, {5, 7},
+    {5, 6}, {0, 4}, {2, 6}, {2, 4}, {1, 5}, {3, 7}, {3, 5}, {1, 2}, {3, 4}};
+
 // Keep the K nearest candidates in (distance^2, index) order.  A squared
 // distance is a non-negative float, so its bits order like the value: each
 // candidate becomes one 64-bit key (d2 bits, index), and keys compare in
 // (distance, index) order with one unsigned comparison.  Up to five kept:
 // the selection network above (23 compare-exchanges); nine: nine rounds of
 // odd-even transposition (36).  Registers only.
+// centre_min: candidate 0 is known to be the smallest key (the descent
+// converged on it); then only the other eight are ordered.
 template <int KMAX>
-__device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, float* out_d2) {
+__device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, float* out_d2, bool centre_min = false) {
     uint64_t key[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) key[a] = ((uint64_t)__float_as_uint(C.d2[a]) << 32) | (uint32_t)C.idx[a];
     if constexpr (KMAX == 1) {
+        if (!centre_min) {
 #pragma unroll
-        for (int a = 1; a < 9; ++a) key[0] = key[a] < key[0] ? key[a] : key[0];
+            for (int a = 1; a < 9; ++a) key[0] = key[a] < key[0] ? key[a] : key[0];
+        }
     } else if constexpr (KMAX <= 5) {
+        if (centre_min) {
 #pragma unroll
-        for (int c = 0; c < kSel5of9; ++c) {
-            const int a = kSel5of9Net[c][0], b = kSel5of9Net[c][1];
-            const uint64_t lo = key[a] < key[b] ? key[a] : key[b];
-            const uint64_t hi = key[a] < key[b] ? key[b] : key[a];
-            key[a] = lo;
-            key[b] = hi;
+            for (int c = 0; c < kSel4of8; ++c) {
+                const int a = kSel4of8Net[c][0] + 1, b = kSel4of8Net[c][1] + 1;
+                const uint64_t lo = key[a] < key[b] ? key[a] : key[b];
+                const uint64_t hi = key[a] < key[b] ? key[b] : key[a];
+                key[a] = lo;
+                key[b] = hi;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kSel5of9; ++c) {
+                const int a = kSel5of9Net[c][0], b = kSel5of9Net[c][1];
+                const uint64_t lo = key[a] < key[b] ? key[a] : key[b];
+                const uint64_t hi = key[a] < key[b] ? key[b] : key[a];
+                key[a] = lo;
+                key[b] = hi;
+            }
         }
     } else {
 #pragma unroll

@@ -11,11 +11,11 @@ import numpy as np
 HDR = os.path.join(os.path.dirname(__file__), "..", "paper_1903_03837_amd", "csrc", "sf_device.hpp")
 
 
-def network():
+def network(name="kSel5of9"):
     src = open(HDR).read()
-    body = re.search(r"kSel5of9Net\[kSel5of9\]\[2\] = \{(.*?)\};", src, re.S).group(1)
+    body = re.search(name + r"Net\[" + name + r"\]\[2\] = \{(.*?)\};", src, re.S).group(1)
     pairs = [(int(a), int(b)) for a, b in re.findall(r"\{(\d+),\s*(\d+)\}", body)]
-    count = int(re.search(r"constexpr int kSel5of9 = (\d+);", src).group(1))
+    count = int(re.search(r"constexpr int " + name + r" = (\d+);", src).group(1))
     assert len(pairs) == count
     return pairs
 
@@ -52,3 +52,22 @@ def test_pruning_is_tight():
         bad = any(apply(t, [(b >> k) & 1 for k in range(9)])[:5] != sorted((b >> k) & 1 for k in range(9))[:5]
                   for b in range(1 << 9))
         assert bad, i
+
+
+def test_four_of_eight_keeps_four_smallest_in_order():
+    """The network used when the centre is known to be the nearest candidate:
+    the four smallest of the other eight keys, in order, for every input of
+    zeros and ones (0-1 principle) and for random distinct keys; every
+    comparator is needed."""
+    net = network("kSel4of8")
+    assert all(0 <= a < b < 8 for a, b in net)
+    for bits in range(1 << 8):
+        v = [(bits >> i) & 1 for i in range(8)]
+        assert apply(net, v)[:4] == sorted(v)[:4], bits
+    rng = np.random.default_rng(6)
+    for _ in range(2000):
+        assert apply(net, list(rng.permutation(8)))[:4] == [0, 1, 2, 3]
+    for i in range(len(net)):
+        t = net[:i] + net[i + 1:]
+        assert any(apply(t, [(b >> k) & 1 for k in range(8)])[:4] != sorted((b >> k) & 1 for k in range(8))[:4]
+                   for b in range(1 << 8)), i
