@@ -395,12 +395,18 @@ __global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) 
     lookup_adjoint_pixel<KMAX, DT, L2>(P, lds[wave], px, py, blockIdx.z);
 }
 
-// Latency-bound (VALU issue ~14 %): K <= 5 is held to 6 waves per SIMD (80
-// VGPRs, no spills; 5 waves at the compiler's own 85 VGPRs), 7 % faster.
-// At 8 waves it spills; K = 9 spills at either bound and keeps the default.
-template <int KMAX, int DT>
+// Each wave's time is mostly the latency of its dependent loads (corner
+// points, then candidate sets, then texels), at ~50 % VALU issue.  K <= 5 is
+// held to 6 waves per SIMD (no spills), which 7 or 8 waves do not beat.
+// OFF32: the field spans at most 4 GiB, so a texel is addressed by a 32-bit
+// byte offset from the field's (uniform) base, one add per texel.
+template <int KMAX, int DT, bool OFF32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ? 6 : 1))) void lookup_kernel(
     LookupParams P) {
+    // the short blend (fewer VALU instructions, more registers) pays for five
+    // neighbours in a field below 4 GiB; K = 1, K = 9 and larger fields keep
+    // the plain form
+    constexpr bool FAST = KMAX == 5 && OFF32;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
@@ -437,6 +443,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     const float sq = sqrt_big(disc);
     const f3 qo = normalize_big(fma3(d, -b - sq, oc));
     const f3 qd = normalize_big(fma3(d, -b + sq, oc));
+    const float dq2 = dist2(qo, qd);  // squared chord between the hits
 
     int ia[KMAX], jb[KMAX];
     float da[KMAX], db[KMAX];
@@ -473,43 +480,112 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
         wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight_big(da[a], P.inv_rM) : 0.0f;
         wb[a] = jb[a] >= 0 ? tent_weight_big(db[a], P.inv_rN) : 0.0f;
     }
-    float wsum = 0.0f;
+    f3 acc = mk3(0.0f, 0.0f, 0.0f);
+    if constexpr (FAST) {
+        // Texel addresses: a 32-bit byte offset from the field's base, origin
+        // row a at ai * row_bytes plus direction column c at co[c]; uncovered
+        // or missing neighbours read texel 0 (weight 0), so every gather is in
+        // range.
+        constexpr uint32_t TB = texel_bytes<DT>();
+        const char* const lf = (const char*)P.lf;
+        const uint32_t row_bytes = (uint32_t)P.N * TB;
+        uint32_t co[KMAX];
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a)
+        for (int c = 0; c < KMAX; ++c) co[c] = (uint32_t)max(jb[c], 0) * TB;
+        auto load_row = [&](int a, f3* row) {
+            const uint32_t ro = ((ia[a] >= 0 && ia[a] < P.orows) ? (uint32_t)ia[a] : 0u) * row_bytes;
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            const bool bad = P.degenerate && ia[a] == jb[c];
-            wsum += bad ? 0.0f : wa[a] * wb[c];
+            for (int c = 0; c < KMAX; ++c) row[c] = load_texel_at<DT>(lf + (ro + co[c]));
+        };
+        // A pair (a, c) is degenerate when origin and direction neighbour are
+        // the same point of one set (M = N).  That point lies within sqrt(da[a])
+        // of qo and sqrt(db[c]) of qd, so |qo - qd|^2 <= (sqrt(da) + sqrt(db))^2
+        // <= 2 (da + db); with a 10 % margin over the FP32 roundings, a chord
+        // longer than that rules every pair out, and the wave blends without
+        // the per-pair test.  The arithmetic is that of the plain form either
+        // way (each product rounded, then added, in the same order).
+        bool maybe_bad = false;
+        if (P.degenerate) {
+            float ma = 0.0f, mb = 0.0f;
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a) {
+                ma = ia[a] >= 0 ? fmaxf(ma, da[a]) : ma;
+                mb = jb[a] >= 0 ? fmaxf(mb, db[a]) : mb;
+            }
+            maybe_bad = !(dq2 > 2.2f * (ma + mb));
         }
-    {
-        f3 acc = mk3(0.0f, 0.0f, 0.0f);
+        const bool fast = __ballot(maybe_bad) == 0;  // wave-uniform
+        float wsum = 0.0f;
+        {
+            // no fused multiply-add here: the plain form's select keeps the
+            // product and the sum apart
+#pragma clang fp contract(off)
+            if (fast) {
+#pragma unroll
+                for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) wsum += wa[a] * wb[c];
+            } else {
+#pragma unroll
+                for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) wsum += ia[a] == jb[c] ? 0.0f : wa[a] * wb[c];
+            }
+        }
         if (wsum > 0.0f) {
             const float inv = 1.0f / wsum;
-            // unconditional, in-range gathers so all KMAX^2 loads issue together;
-            // a texel's address is its origin row's base plus its column offset
+            // origin rows in turn, the next row's loads in flight while a row is
+            // blended (two rows of texels held)
+            f3 row[2][KMAX];
+            load_row(0, row[0]);
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a) {
+                if (a + 1 < KMAX) load_row(a + 1, row[(a + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) {
+                    const float w = wa[a] * wb[c] * inv;
+                    acc = fma3(row[a & 1][c], (fast || ia[a] != jb[c]) ? w : 0.0f, acc);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+        // plain form: every pair tested, the compiler's own load order
+        float wsum = 0.0f;
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+                const bool bad = P.degenerate && ia[a] == jb[c];
+                wsum += bad ? 0.0f : wa[a] * wb[c];
+            }
+        if (wsum > 0.0f) {
+            const float inv = 1.0f / wsum;
 #pragma unroll
             for (int a = 0; a < KMAX; ++a)
 #pragma unroll
                 for (int c = 0; c < KMAX; ++c) {
                     const bool bad = P.degenerate && ia[a] == jb[c];
                     const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
-                    // unconditional, in-range gathers so all KMAX^2 loads issue together
                     const int ai = (ia[a] >= 0 && ia[a] < P.orows) ? ia[a] : 0;
                     const uint64_t t = (uint64_t)ai * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
                     acc = fma3(load_texel<DT>(P.lf, t), w, acc);
                 }
         }
-        float* o = P.img + 3 * pix;
-        o[0] = acc.x;
-        o[1] = acc.y;
-        o[2] = acc.z;
     }
+    float* o = P.img + 3 * pix;
+    o[0] = acc.x;
+    o[1] = acc.y;
+    o[2] = acc.z;
 }
 
 template <int KMAX, int DT>
 static hipError_t launch_lookup_mode(const LookupParams& P, int mode, hipStream_t s) {
     dim3 grid((P.W + 15) / 16, (P.H + 15) / 16, P.nviews);
-    if (mode == 0) lookup_kernel<KMAX, DT><<<grid, 256, 0, s>>>(P);
+    const bool off32 = (uint64_t)P.orows * (uint64_t)P.N * (uint64_t)texel_bytes<DT>() <= (1ull << 32);
+    if (mode == 0 && off32) lookup_kernel<KMAX, DT, true><<<grid, 256, 0, s>>>(P);
+    else if (mode == 0) lookup_kernel<KMAX, DT, false><<<grid, 256, 0, s>>>(P);
     else if (mode == 1) lookup_adjoint_kernel<KMAX, 0, false><<<grid, 256, 0, s>>>(P);
     else lookup_adjoint_kernel<KMAX, DT, true><<<grid, 256, 0, s>>>(P);
     return hipGetLastError();
