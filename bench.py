@@ -44,11 +44,13 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the sources the generation kernel and its launch are built
+    from (the kernel, its headers, the set-up kernels and the entry points);
+    the lookup and metric kernels are not part of it."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1903_03837_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("api.cpp", "generate.hip", "internal.hpp", "sf_device.hpp", "tracer_device.hpp", "wave.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
