@@ -226,11 +226,18 @@ def sweep_configs(configs, with_oracle=True, calib_copy_mb=0):
         del lf
         torch.cuda.empty_cache()
     if calib_copy_mb:
+        # counter calibration: a plain device copy of calib_copy_mb MiB, then
+        # gathers of 4 and of 16 bytes from each 128-byte line of it, lines
+        # in random order (64-bit indices, one per line)
         n = calib_copy_mb * (1 << 20) // 4
         a_ = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
         b_ = torch.empty_like(a_)
         b_.copy_(a_)
+        lines = torch.randperm(n // 32, device=dev, generator=torch.Generator(device=dev).manual_seed(7))
+        g4 = a_[lines * 32]
+        g16 = a_.view(-1, 4)[lines * 8]
         torch.cuda.synchronize()
+        del g4, g16, lines, a_, b_
 
 
 def timed_ms(fn, reps, stream):
