@@ -297,12 +297,14 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
             // for both searches' candidate sets at once)
             {
                 Cand9 C;
-                sf_nearest(P.M, P.invM, SfTable{P.tab_o}, qo, sf_zone(P.M, qo.z), C);
+                const int ko = sf_zone(P.M, qo.z);
+                sf_nearest(P.M, P.invM, SfTable{P.tab_o}, qo, ko, P.zone_o[ko], C);
                 select_k<KMAX>(C, P.K, ia, da);
             }
             {
                 Cand9 C;
-                sf_nearest(P.N, P.invN, SfTable{P.tab_d}, qd, sf_zone(P.N, qd.z), C);
+                const int kd = sf_zone(P.N, qd.z);
+                sf_nearest(P.N, P.invN, SfTable{P.tab_d}, qd, kd, P.zone_d[kd], C);
                 select_k<KMAX>(C, P.K, jb, db);
             }
             if constexpr (!L2) {
@@ -680,7 +682,7 @@ __global__ void query_kernel(int n, float inv_n, float inv_r, const float* query
     const f3 v = normalize(mk3(query[3 * q], query[3 * q + 1], query[3 * q + 2]));
     Cand9 C;
     const int k = sf_zone(n, v.z);
-    sf_nearest(n, inv_n, SfEval{n, inv_n}, v, k, C);
+    sf_nearest(n, inv_n, SfEval{n, inv_n}, v, k, sf_zone_basis(k, inv_n), C);
     int id[KMAX];
     float d2[KMAX];
     select_k<KMAX>(C, K, id, d2);

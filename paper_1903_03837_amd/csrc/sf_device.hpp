@@ -228,11 +228,12 @@ __device__ __forceinline__ void sf_candidates(int n, const Pts& pts, f3 q, int k
 }
 
 // Nearest point: lattice corners, then descent over the candidate set until
-// the centre is the closest candidate.  Leaves that final set in C.
+// the centre is the closest candidate.  Leaves that final set in C.  Z: the
+// basis of zone k (sf_zone_basis).
 template <class Pts>
-__device__ __forceinline__ int sf_nearest(int n, float inv_n, const Pts& pts, f3 q, int k, Cand9& C) {
+__device__ __forceinline__ int sf_nearest(int n, float inv_n, const Pts& pts, f3 q, int k, const SfZone& Z, Cand9& C) {
     float bd;
-    int c = sf_cell_nearest(n, inv_n, pts, q, k, bd);
+    int c = sf_cell_nearest_z(n, inv_n, pts, q, Z, bd);
     for (int it = 0; it < 16; ++it) {
         sf_candidates(n, pts, q, k, c, C);
         int best = C.idx[0];
