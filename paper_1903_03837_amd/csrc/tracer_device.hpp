@@ -424,7 +424,7 @@ struct GridWalk {
             const float2 m = mg[ci];
             const float s = m.x;
             const float tmin = fminf(fminf(tx, ty), tz);
-            const float te = fminf(tmin, tend);
+            const float te = __builtin_amdgcn_fmed3f(tmin, tend, -3.402823466e38f);  // min(tmin, tend)
             const float room = s * fmaxf(te - t, 0.0f);
             const float th = fmaf(tau, m.y, t);        // the current target's point (s > 0 when it lies here)
             const bool hitA = seekA && tau < room;     // A lies in this cell
@@ -447,7 +447,7 @@ struct GridWalk {
             const bool bx = tx == tmin, by = !bx && ty == tmin, bz = !bx && !by;
             // (exactly one of bx, by, bz holds: a sum of selects, not an indexed pick)
             const int st = (bx ? sx : 0) + (by ? sy : 0) + (bz ? sz : 0);
-            ci = min(max(ci + st, 0), last);
+            ci = (int)min((unsigned)(ci + st), (unsigned)last);  // (a wrapped index clamps to last)
             tx += bx ? dx : 0.0f;
             ty += by ? dy : 0.0f;
             tz += bz ? dz : 0.0f;
