@@ -549,6 +549,8 @@ def main():
             "hbm_frac": (traffic / gen_s / PEAK_HBM) if traffic else None,
             "launch_ms": legs["generate"],
             "ops_per_point": OPS_POINT,
+            "ops_model": "algorithmic count, not counters: per tentative point (tentative collision or shadow "
+                         "step) ~40 FP32 ops + one Philox4x32-10 call (60) + one logarithm (4)",
             "ops_per_launch": OPS_POINT * points,
             "units_per_launch": {"tentative_points": points, "tentative_collisions": tent, "shadow_steps": shadow,
                                  "real_collisions": real, "samples": samples, "traced_samples": traced,
