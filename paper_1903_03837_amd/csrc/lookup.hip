@@ -397,9 +397,10 @@ __global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) 
     lookup_adjoint_pixel<KMAX, DT, L2>(P, lds[wave], px, py, blockIdx.z);
 }
 
-// Bound by VALU issue (~90 % of cycles at K = 5): the searches, the
-// selection and the blend.  K <= 5 is held to 6 waves per SIMD (no spills),
-// which 7 or 8 waves do not beat.
+// Bound by VALU issue (the searches, the selection and the blend) while the
+// field stays in the caches; on a field of many GB the gathers' misses to
+// HBM take their share too.  K <= 5 is held to 6 waves per SIMD (no
+// spills), which 7 or 8 waves do not beat.
 // OFF32: the field spans at most 4 GiB, so a texel is addressed by a 32-bit
 // byte offset from the field's (uniform) base, one add per texel.
 template <int KMAX, int DT, bool OFF32>
