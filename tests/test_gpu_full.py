@@ -7,6 +7,7 @@ and the differentiation workload's gradient checks at full size.
     generation takes when M * N * spp exceeds 2^31;
   - the paper's storage configuration (M = 12288 with the upper hemisphere of
     origins stored, N = 23576; Sec. 3), with a lookup of 1920 x 1080 views;
+  - the lookup on fields above 4 GiB (N = 32768, FP32 and FP16);
   - the differentiation workload (128^3 f32, N = 1024, 32 spp, 16 views of
     512^2): adjoint against the oracle gradient on 20000 rays and against
     central differences (h = 1e-3) of the frozen-sampling forward.
@@ -140,6 +141,51 @@ def test_paper_storage_config(lp, orc):
     assert np.array_equal(g_nn[clear], onn[clear])
     tol = 3e-5 / np.sqrt(4 * np.pi / M) * float(lf_host.max() - lf_host.min())
     assert np.abs(g_img[clear] - rgb[clear]).max() <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_lookup_wide_field(lp, orc, dtype):
+    """Lookup on a field above 4 GiB (M = N = 32768: 12.9 GB in FP32, 6.4 GB in
+    FP16), whose texel byte offsets exceed 2^32: 2 views of 1920 x 1080 at
+    K = 5 and K = 1 over a seeded random field, against the oracle on 3000
+    sampled pixels (nearest pair exact, RGB within the lookup bar)."""
+    need_memory(40)
+    M = N = 32768
+    W, H = 1920, 1080
+    sc = S.config(2, M=M, N=N, views=2, width=W, height=H)
+    prm = lp.GenParams(M=M, N=N, radius=sc.params.radius)
+    cams = [lp.Camera(c.eye, c.target, c.up, c.vfov) for c in sc.cams]
+    g = torch.Generator(device="cuda").manual_seed(61)
+    lf = torch.empty((M, N, 3), dtype=torch.float32, device="cuda")
+    for r0 in range(0, M, 4096):
+        lf[r0:r0 + 4096] = torch.rand((4096, N, 3), generator=g, device="cuda")
+    if dtype == "f16":
+        lf = lf.half()
+    lf_host = lf.float().cpu().numpy()
+    rng = np.random.default_rng(62)
+    pix = np.stack([rng.integers(0, 2, 3000), rng.integers(0, W, 3000), rng.integers(0, H, 3000)], 1).astype(np.int32)
+    flat = (pix[:, 0].astype(np.int64) * H + pix[:, 2]) * W + pix[:, 1]
+    idx = torch.from_numpy(flat).cuda()
+    tol = 3e-5 / np.sqrt(4 * np.pi / M) * float(lf_host.max() - lf_host.min())
+    for K in (5, 1):
+        img, nn = lp.lookup(lf, prm, cams, W, H, K=K, with_nn=True)
+        torch.cuda.synchronize()
+        g_img = img.reshape(-1, 3)[idx].cpu().numpy()
+        g_nn = nn.reshape(-1, 2)[idx].cpu().numpy()
+        rgb, onn, mg = orc.lookup(lf_host, sc.params, sc.cams, W, H, K, pix)
+        clear = (mg[:, 0] > 1e-4) & (mg[:, 1] > 1e-4) & (mg[:, 2] > 1e-3) & ((mg[:, 3] > 1e-4) | (K == 1))
+        assert clear.mean() > 0.99
+        assert np.array_equal(g_nn[clear], onn[clear])
+        err = np.abs(g_img[clear] - rgb[clear])
+        print(f"wide field {dtype} K={K}: max |err| {err.max():.2e} (tol {tol:.2e}), "
+              f"{(~clear).sum()} of {len(clear)} pixels in a decision band")
+        assert err.max() <= tol
+        if K == 1:
+            assert np.array_equal(g_img[clear], rgb[clear])
+    # some sampled texels lie beyond byte offset 2^32
+    tb = 12 if dtype == "f32" else 6
+    hit = onn[:, 0] >= 0
+    assert (onn[hit, 0].astype(np.int64) * N + onn[hit, 1]).max() * tb > (1 << 32)
 
 
 def test_c5_gradient_full_size(lp, orc):

@@ -370,7 +370,7 @@ def lookup_case(lp, orc, M, N, views, W, H, K, dtype="f32", seed=0, pix=None):
     return g_img[flat], g_nn[flat], rgb, onn, clear, lookup_tol(M, N, lf_host)
 
 
-@pytest.mark.parametrize("K", [1, 5, 9])
+@pytest.mark.parametrize("K", [1, 3, 5, 9])
 def test_lookup_small(lp, orc, K):
     g_img, g_nn, rgb, onn, clear, tol = lookup_case(lp, orc, 256, 256, 3, 72, 40, K)
     err = np.abs(g_img[clear] - rgb[clear])
