@@ -44,13 +44,18 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the sources the generation kernel and its launch are built
-    from (the kernel, its headers, the set-up kernels and the entry points);
-    the lookup and metric kernels are not part of it."""
+    """Hash of the code the generation kernel and its launch are built from
+    (the kernel, its headers, the set-up kernels and the entry points), with
+    comments and blank space removed so that editing a comment keeps a
+    profile valid; the lookup and metric kernels are not part of it."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1903_03837_amd", "csrc")
     for f in ("api.cpp", "generate.hip", "internal.hpp", "sf_device.hpp", "tracer_device.hpp", "wave.hip"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        text = open(os.path.join(csrc, f), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

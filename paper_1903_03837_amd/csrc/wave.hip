@@ -7,7 +7,9 @@
 // long as its most expensive lane; measured lane utilisation was 17 %.  Here
 // every lane runs its own state machine
 //     IDLE -> START -> FLIGHT -> VERTEX -> SHADOW -> SCATTER -> FLIGHT ... -> IDLE
-// and every loop iteration advances all lanes by one Philox4x32-10 block:
+// and each loop iteration advances every lane by one Philox4x32-10 block
+// (further passes of the same iteration advance only the lanes still
+// tracking a segment, while at least kTrackPass of the 64 do):
 //   START   pair 0 jitters the origin, pair 1 is the first tentative collision;
 //   FLIGHT  two tentative collisions (delta tracking; the majorant grid is
 //           walked from the current point to each of them);
@@ -19,9 +21,10 @@
 // a wave that holds all three pays for each once.
 // Both tentative points of a block are fetched before either is classified,
 // so a lane keeps 16 voxel loads in flight.  A lane whose sample ends starts
-// the next sample of its ray in the next iteration; a lane whose ray is done
-// takes the next ray of its wave's current 8 x 8 tile, and the wave takes a
-// new tile when the current one is used up (one atomic per tile).
+// the next sample of its work item (a range of one ray's samples) in the
+// next iteration; a lane whose work item is done takes the next one of its
+// wave's current 8 x 8 tile of rays, and the wave takes a new tile when the
+// current one is used up (one atomic per tile).
 //
 // Ray order: origins and directions are each sorted into latitude bands of
 // ~5 sqrt(n) consecutive SF indices, by azimuth inside a band, so a tile's
