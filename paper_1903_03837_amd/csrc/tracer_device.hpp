@@ -391,7 +391,7 @@ struct GridWalk {
     // tauA (when wantA), then point B for tauB from A.  One loop for both
     // keeps the wave's trip count at the maximum over lanes of the cells both
     // points need, not the sum of two maxima.  Points past the segment come
-    // back as tend, with the majorant of their cell in sbA / sbB.
+    // back as tend (their majorant is then not used).
     // One trip handles one cell: point A if it lies in the cell, then point B
     // if it lies in the rest of the same cell, else the exponential variate
     // left over and either the segment's end or a step into the next cell.
@@ -418,11 +418,15 @@ struct GridWalk {
         bool seekA = wantA;  // still looking for A (else for B)
         float tau = wantA ? tauA : tauB;
         tA = t;
-        tB = tend;
         tend = __builtin_canonicalizef(tend);
+        // B is found, if at all, in the last trip: its point and majorant are
+        // taken from that trip after the loop; A not found by the end of the
+        // segment lies at tend
+        float s, thb;
+        bool hitB;
         for (;;) {
             const float2 m = mg[ci];
-            const float s = m.x;
+            s = m.x;
             const float tmin = fminf(fminf(tx, ty), tz);
             const float te = __builtin_amdgcn_fmed3f(tmin, tend, -3.402823466e38f);  // min(tmin, tend)
             const float room = s * fmaxf(te - t, 0.0f);
@@ -432,14 +436,12 @@ struct GridWalk {
             const float tb0 = hitA ? th : t;
             const float taub = hitA ? tauB : tau;
             const float roomb = hitA ? s * fmaxf(te - th, 0.0f) : room;
-            const float thb = hitA ? fmaf(taub, m.y, tb0) : th;
-            const bool hitB = (hitA || !seekA) && taub < roomb;
+            thb = hitA ? fmaf(taub, m.y, tb0) : th;
+            hitB = (hitA || !seekA) && taub < roomb;
             const bool end = !hitB && te >= tend;        // the segment ends in this cell
             const bool step = !hitB && !end;             // on into the next cell
-            tA = hitA ? th : ((end && seekA) ? tend : tA);
+            tA = hitA ? th : tA;
             sbA = hitA ? s : sbA;
-            tB = hitB ? thb : tB;
-            sbB = hitB ? s : sbB;
             t = te;
             tau = taub - roomb;
             seekA = seekA && !hitA;
@@ -453,6 +455,9 @@ struct GridWalk {
             tz += bz ? dz : 0.0f;
             if (!step) break;
         }
+        tA = seekA ? tend : tA;
+        tB = hitB ? thb : tend;
+        sbB = s;
     }
 };
 
