@@ -35,6 +35,13 @@ sys.path.insert(0, ROOT)
 # multiplies and 4 xors) and one logarithm (4).  Peak: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz, one 32-bit lane operation per lane and clock.
 OPS_POINT = 40 + 60 + 4
+# Resident waves per SIMD of the forward tracer (lf_gen_params.waves_per_simd;
+# results do not depend on it).  Four is the library's default and the faster
+# choice on every workload measured but the precision workload, whose
+# transfer function makes the tracer run HBM at ~77 % of its peak: there four
+# waves' extra concurrent misses cost more than the latency they hide
+# (4776 against 4530 ms per generation).
+WAVES = {4: 3}
 PEAK_OPS = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
 
@@ -122,6 +129,7 @@ def sweep_configs(configs, with_oracle=True, calib_copy_mb=0):
         log(f"configs: workload c{c}")
         sc = S.config(c)
         vol, med, light, prm, cams = lp.device_scene(sc)
+        prm = dataclasses.replace(prm, waves_per_simd=WAVES.get(c, 0))
         M, N, spp = prm.M, prm.N, prm.spp
         stats = torch.zeros(5, dtype=torch.int64, device=dev)
         lf = lp.generate(vol, med, light, prm, stats=stats)
@@ -444,6 +452,7 @@ def main():
     log("bench: building the precision workload (512^3 u16 phantom in 8^3 bricks, N=32768, 16 spp)")
     sc = S.config(4, views=32, width=1920, height=1080)
     vol, med, light, prm, cams = lp.device_scene(sc)
+    prm = dataclasses.replace(prm, waves_per_simd=WAVES[4])
     V, W, H, K = len(cams), sc.width, sc.height, sc.K
     M, N, spp = prm.M, prm.N, prm.spp
     lf = torch.empty((M, N, 3), dtype=torch.float32, device=dev)
@@ -540,6 +549,7 @@ def main():
                         "grid, FP32 light field (12.9 GB); lookup of 32 views 1920x1080 K=5",
             "M": M, "N": N, "spp": spp, "max_bounces": prm.max_bounces, "views": V, "width": W, "height": H,
             "K": K, "volume": "512^3 u16 8^3-bricked", "majorant_grid": prm.grid,
+            "waves_per_simd": prm.waves_per_simd,
         },
         "roofline": {
             "kernel": "gen_wave_kernel<u16, forward> (lf_generate)",

@@ -134,7 +134,14 @@ typedef struct {
  * that misses the volume box in every sample only the last sample is);
  * lf_generate_backward reads it instead of tracing each sample a first
  * time.  It must come from lf_generate with the same parameters and medium
- * and sample == NULL. */
+ * and sample == NULL.
+ * waves_per_simd: the resident waves per SIMD the forward light-field and
+ * view kernels' registers are budgeted for (0 = 4; otherwise 3 or 4, else
+ * LF_E_ARG).  Results do not depend on it: the same code draws the same
+ * random numbers in the same order.  Four waves hide more latency and suit
+ * workloads whose volume traffic HBM absorbs; when the tracer already runs
+ * HBM near its peak, three are faster (fewer concurrent misses).
+ * lf_generate_backward always budgets for three. */
 typedef struct {
     int32_t M, N;
     float center[3];
@@ -151,6 +158,7 @@ typedef struct {
     int32_t surface;        /* 1: isosurface variant at raw value iso */
     float iso;
     float* sample_radiance; /* NULL or device float32 [origin_rows][N][spp][3] */
+    int32_t waves_per_simd; /* forward path tracer's register budget: 0 = the library's choice (4), 3 or 4 */
 } lf_gen_params;
 
 /* Pinhole view (host array): pixel (x, y) looks through its centre, row 0 at

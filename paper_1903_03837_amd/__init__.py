@@ -66,7 +66,8 @@ class _GenParams(C.Structure):
                 ("majorant_grid", C.c_int32),
                 ("seed", C.c_uint64), ("jitter", C.c_int32), ("origin_rows", C.c_int32),
                 ("row_begin", C.c_int64), ("row_end", C.c_int64), ("stats", C.c_void_p),
-                ("surface", C.c_int32), ("iso", C.c_float), ("sample_radiance", C.c_void_p)]
+                ("surface", C.c_int32), ("iso", C.c_float), ("sample_radiance", C.c_void_p),
+                ("waves_per_simd", C.c_int32)]
 
 
 class _Camera(C.Structure):
@@ -216,6 +217,7 @@ class GenParams:
     grid: int = 0                            # majorant grid cells per axis (0: one global majorant)
     surface: int = 0                         # 1: isosurface variant at raw value iso
     iso: float = 0.0
+    waves_per_simd: int = 0                  # forward tracer's register budget: 0 (library's choice), 3 or 4
 
     @property
     def rows(self) -> int:
@@ -230,6 +232,7 @@ class GenParams:
         s.hg_g, s.majorant = self.g, self.majorant
         s.majorant_grid = self.grid
         s.surface, s.iso = self.surface, self.iso
+        s.waves_per_simd = self.waves_per_simd
         s.seed = self.seed
         s.jitter = self.jitter
         s.origin_rows = self.origin_rows

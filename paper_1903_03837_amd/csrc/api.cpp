@@ -123,6 +123,8 @@ int check_params(const lf_gen_params* p, bool need_rays) {
     if (p->majorant_grid < 0 || p->majorant_grid > 16)
         return fail(LF_E_ARG, "majorant_grid must be in [0, 16] (got %d)", p->majorant_grid);
     if (p->surface != 0 && p->surface != 1) return fail(LF_E_ARG, "surface must be 0 or 1");
+    if (p->waves_per_simd != 0 && p->waves_per_simd != 3 && p->waves_per_simd != 4)
+        return fail(LF_E_ARG, "waves_per_simd must be 0, 3 or 4 (got %d)", p->waves_per_simd);
     if (!std::isfinite(p->iso)) return fail(LF_E_ARG, "iso must be finite");
     if (p->sample_radiance && p->surface)
         return fail(LF_E_UNSUPPORTED, "sample_radiance is not available in the isosurface variant");
@@ -187,6 +189,7 @@ int check_light(const lf_light* l) {
 void pack_trace(lp::TraceParams& T, const lf_volume* v, const lf_medium* e, const lf_medium* s,
                 const lf_light* l, const lf_gen_params* p) {
     std::memset(&T, 0, sizeof(T));
+    T.waves = p->waves_per_simd == 3 ? 3 : 4;
     T.vol = v->data;  // replaced by the workspace's halo-brick copy
     T.nx = v->nx;
     T.ny = v->ny;

@@ -82,6 +82,7 @@ struct TraceParams {
     int32_t dtype;
     unsigned long long* stats;
     int32_t part_log2;  // work items per ray = 2^part_log2 sample ranges
+    int32_t waves;      // forward kernels: waves per SIMD the registers are budgeted for (3 or 4)
     float* part_sums;   // forward with several ranges: [rows][N][ranges][3]
     // SF points of both sets (workspace tables filled by sf_point with
     // inv_n = 1/n in FP32, the values the kernel would compute)

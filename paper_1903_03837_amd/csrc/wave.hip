@@ -52,8 +52,11 @@ namespace lp {
 // the plain kernel spends no registers on them).  VIEWS: ground-truth views
 // (pinhole rays of pixel tiles) instead of light-field rays, also a separate
 // instantiation so that the light-field kernel carries none of its code.
-template <int VT, int MODE, bool STATS, bool VIEWS>
-__global__ __launch_bounds__(256, 3) void gen_wave_kernel(TraceParams P) {
+// WAVES: resident waves per SIMD the registers are budgeted for (3: up to 168
+// VGPRs; 4: 128, with a few values spilled).  The code and its results are
+// the same; four waves hide more latency where HBM has room to spare.
+template <int VT, int MODE, bool STATS, bool VIEWS, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void gen_wave_kernel(TraceParams P) {
     extern __shared__ float4 smem[];
     float4* lut_e = smem;
     float4* lut_s = smem + (MODE == kFrozen ? P.lut_n : 0);
@@ -686,8 +689,8 @@ hipError_t launch_active_rays(const TraceParams& P, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int VT, int MODE, bool STATS, bool VIEWS>
-static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
+template <int VT, int MODE, bool STATS, bool VIEWS, int WAVES>
+static hipError_t launch_wave_w(const TraceParams& P, hipStream_t s) {
     const long long rows = P.row_end - P.row_begin;
     const long long ntiles = (P.views ? (long long)P.nviews * P.vtiles : ((rows + 7) / 8) * (long long)((P.N + 7) / 8))
                              << P.part_log2;
@@ -700,15 +703,25 @@ static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE, STATS, VIEWS>, 256, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_wave_kernel<VT, MODE, STATS, VIEWS, WAVES>, 256,
+                                                         lds);
     if (e != hipSuccess) return e;
     long long blocks = (long long)cus * (per_cu > 0 ? per_cu : 1);
     // at least one tile per wave (list lengths are only known on the device;
     // waves that find no chunk exit at once)
     const long long need = (ntiles + 3) / 4;
     if (blocks > need) blocks = need;
-    gen_wave_kernel<VT, MODE, STATS, VIEWS><<<(unsigned)blocks, 256, lds, s>>>(P);
+    gen_wave_kernel<VT, MODE, STATS, VIEWS, WAVES><<<(unsigned)blocks, 256, lds, s>>>(P);
     return hipGetLastError();
+}
+
+// The adjoint is budgeted for three waves (at four it spills ~32 values and
+// runs slower); the forward modes take P.waves.
+template <int VT, int MODE, bool STATS, bool VIEWS>
+static hipError_t launch_wave_t(const TraceParams& P, hipStream_t s) {
+    if constexpr (MODE != kGrad)
+        if (P.waves == 4) return launch_wave_w<VT, MODE, STATS, VIEWS, 4>(P, s);
+    return launch_wave_w<VT, MODE, STATS, VIEWS, 3>(P, s);
 }
 
 template <int VT>

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header(lp):
     assert C.sizeof(lp._Volume) == 64
     assert C.sizeof(lp._Medium) == 16
     assert C.sizeof(lp._Light) == 76
-    assert C.sizeof(lp._GenParams) == 104
+    assert C.sizeof(lp._GenParams) == 112
     assert C.sizeof(lp._Camera) == 40
 
 

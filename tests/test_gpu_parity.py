@@ -151,6 +151,29 @@ def test_generate_c1_full(lp, orc):
     assert abs(st[0] / ost[0] - 1) < 1e-3 and abs(st[1] / ost[1] - 1) < 1e-3
 
 
+def test_waves_per_simd_leaves_results_unchanged(lp):
+    """The forward tracer budgeted for 3 or 4 waves per SIMD runs the same
+    code on the same random numbers: the light field (plain, with work
+    counts, with frozen sampling), the kept sample radiance and the
+    ground-truth views are bit-identical; other values are rejected."""
+    sc = S.config(2, M=256, N=256, spp=8, views=2, width=96, height=64)
+    vol, med, light, prm, cams = lp.device_scene(sc)
+    out = {}
+    for w in (3, 4):
+        p = dataclasses.replace(prm, waves_per_simd=w)
+        srad = torch.zeros((256, 256, 8, 3), dtype=torch.float32, device="cuda")
+        stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+        lf = lp.generate(vol, med, light, p, stats=stats, sample_radiance=srad)
+        frozen = lp.generate(vol, lp.Medium(med.lut * 0.9, med.scale), light, p, sample=med)
+        views = lp.render_views(vol, med, light, p, cams, 96, 64)
+        torch.cuda.synchronize()
+        out[w] = (lf, srad, stats, frozen, views)
+    for a, b in zip(out[3], out[4]):
+        assert torch.equal(a, b)
+    with pytest.raises(lp.LumiPathError):
+        lp.generate(vol, med, light, dataclasses.replace(prm, waves_per_simd=5))
+
+
 def test_generate_c5_sampled(lp, orc):
     """Differentiation workload (f32 volume) at full size, 20000 sampled rays."""
     sc = S.config(5)
