@@ -430,8 +430,8 @@ def main():
                     help="instead of the step, measure generation on these workloads (e.g. 1,2,3,4,5)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (the light field shards by rows "
-              "of origins; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the light field would shard by "
+              "slabs of origin rows, one per GPU). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.configs:
         sweep_configs([int(c) for c in args.configs.split(",")], with_oracle=not args.no_cpu_baseline,
