@@ -5,10 +5,10 @@
  * speed: every quantity is computed in double precision, straight from its
  * definition, in the order the method states it.  Citations name the
  * section, equation or paragraph of Fink et al. 2019 (arXiv 1903.03837).
- * The volumetric path tracer is the repository's reading of "a conventional
- * path tracer comparable to PBRT" (Sec. 2) applied to a density volume; its
- * conventions (random-number counters, majorant, jitter frame, lights) are
- * listed in the design notes and restated at each step below.
+ * The volumetric path tracer is the repository's reading of the paper's
+ * conventional, PBRT-like path tracer (Sec. 2) applied to a density volume;
+ * its conventions (random-number counters, majorant, jitter frame, lights)
+ * are stated at each step below.
  */
 #include "lforacle.h"
 

@@ -7,8 +7,8 @@
  * GPU product path never calls it and shares no code, header or table with
  * it.  Everything is computed in double precision from the definitions in
  * Fink et al., "LumiPath -- Towards Real-time Physically-based Rendering on
- * Embedded Devices" (arXiv 1903.03837), with the readings of silent passages
- * listed in the repository's design notes.
+ * Embedded Devices" (arXiv 1903.03837); where the paper is silent, the
+ * reading taken is stated beside the function that takes it.
  *
  * Parity status of each function (what pins it) is stated beside it.
  */
