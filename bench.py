@@ -552,7 +552,7 @@ def main():
             "waves_per_simd": prm.waves_per_simd,
         },
         "roofline": {
-            "kernel": "gen_wave_kernel<u16, forward> (lf_generate)",
+            "kernel": f"gen_wave_kernel<u16, forward, {prm.waves_per_simd or 4} waves per SIMD> (lf_generate)",
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_OPS / 1e12,
