@@ -38,7 +38,9 @@ FLIPS = {"c1": 1e-4, "c2": 3e-4, "c5": 3e-4}
 
 
 def lookup_tol(M, N, lf):
-    r = math.sqrt(4 * math.pi / min(M, N))
+    # a tent weight moves by ~1e-6 / r under the FP32 rounding of the hits,
+    # most for the finer of the two point sets (the larger n)
+    r = math.sqrt(4 * math.pi / max(M, N))
     return LOOKUP_C / r * float(lf.max() - lf.min())
 
 
@@ -412,6 +414,23 @@ def test_lookup_small(lp, orc, K):
 def test_lookup_half_storage(lp, orc, dtype):
     g_img, g_nn, rgb, onn, clear, tol = lookup_case(lp, orc, 200, 180, 2, 48, 36, 5, dtype=dtype, seed=3)
     assert np.array_equal(g_nn[clear], onn[clear])
+    check_pixels(g_img[clear], rgb[clear], tol)
+
+
+@pytest.mark.parametrize("M,N", [(65535, 1024), (1024, 65535)])
+@pytest.mark.parametrize("K", [1, 5])
+def test_lookup_largest_point_sets(lp, orc, M, N, K):
+    """The largest SF sets the lookup takes (65535 points, the top zones of
+    the inverse mapping), for the origins and for the directions, with the
+    other set small: 3000 sampled pixels of 2 views of 640 x 360."""
+    rng = np.random.default_rng(71)
+    V, W, H = 2, 640, 360
+    pix = np.stack([rng.integers(0, V, 3000), rng.integers(0, W, 3000), rng.integers(0, H, 3000)], 1)
+    g_img, g_nn, rgb, onn, clear, tol = lookup_case(lp, orc, M, N, V, W, H, K, seed=72, pix=pix.astype(np.int32))
+    assert clear.mean() > 0.99
+    assert np.array_equal(g_nn[clear], onn[clear])
+    if K == 1:
+        assert np.array_equal(g_img[clear], rgb[clear])
     check_pixels(g_img[clear], rgb[clear], tol)
 
 
