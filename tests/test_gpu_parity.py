@@ -210,6 +210,20 @@ def test_generate_ragged_and_tiny(lp, orc):
             assert rel_l1(got[nd], ref[nd]) <= RAD_TOL, (M, N)
 
 
+@pytest.mark.parametrize("M,N", [(65535, 8), (8, 65535)])
+def test_generate_largest_point_sets(lp, orc, M, N):
+    """The largest SF sets generation takes (65535 points: the FP64 golden-
+    ratio step at its largest index) as origins or as directions, with a
+    tiny other set (524 280 rays, 4 spp): 20000 sampled rays against the
+    oracle, and every texel finite."""
+    sc = S.config(1, M=M, N=N, spp=4)
+    got = gpu_field(lp, sc)
+    ks = S.random_rays(M, N, 20000, 73)
+    ref = orc.generate(sc, ks)
+    assert np.all(np.isfinite(got))
+    bars.check(got[ks], ref, FLIPS["c1"] * 5, f"M={M} N={N} (20000 rays)")
+
+
 # ------------------------------------------------------------ majorant grid
 @pytest.mark.parametrize("c,G,vol_n", [(1, 16, None), (1, 7, None), (2, 16, 64), (3, 16, 64), (5, 11, 32)])
 def test_majorant_grid_matches_oracle(lp, orc, c, G, vol_n):
