@@ -268,10 +268,17 @@ def test_row_slabs_bit_identical(lp):
     vol, med, light, prm, _ = lp.device_scene(sc)
     full = lp.generate(vol, med, light, prm)
     part = torch.zeros_like(full)
-    for a, b in [(0, 21), (21, 22), (22, 64)]:
+    for a, b in [(0, 21), (21, 22), (22, 22), (22, 64), (64, 64)]:  # (empty ranges write nothing)
         lp.generate(vol, med, light, dataclasses.replace(prm, row_begin=a, row_end=b), out=part)
     torch.cuda.synchronize()
     assert torch.equal(full, part)
+    # an empty range leaves the output as it was, with and without the kept sample radiance
+    sentinel = torch.full_like(full, -7.0)
+    srad = torch.full((64, 64, 4, 3), -7.0, device="cuda")
+    lp.generate(vol, med, light, dataclasses.replace(prm, row_begin=30, row_end=30), out=sentinel,
+                sample_radiance=srad)
+    torch.cuda.synchronize()
+    assert bool((sentinel == -7.0).all()) and bool((srad == -7.0).all())
 
 
 def test_bricked_equals_linear(lp, orc):
