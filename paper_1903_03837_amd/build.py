@@ -23,6 +23,13 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
+# Per-source flags.  The lookup kernels are built without floating-point
+# contraction: every product and sum is rounded on its own unless the source
+# writes fmaf, so the forward lookup and the fused lookup + loss, two kernels
+# with different register budgets, form each view value with the same
+# roundings whatever the compiler fuses in either.
+SOURCE_FLAGS = {"lookup.hip": ["-ffp-contract=off"]}
+
 
 def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -33,7 +40,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src: str) -> str:
         obj = os.path.join(BUILD, src + ".o")
-        cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd.insert(1, "-x")
             cmd.insert(2, "hip")

@@ -19,6 +19,7 @@
 #include <mutex>
 
 #include "internal.hpp"
+#include "sf_search.hpp"
 
 namespace lp {
 
@@ -296,16 +297,12 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
             // (one search after the other: the scatter's registers leave no room
             // for both searches' candidate sets at once)
             {
-                Cand9 C;
                 const int ko = sf_zone(P.M, qo.z);
-                sf_nearest(P.M, P.invM, SfTable{P.tab_o}, qo, ko, P.zone_o[ko], C);
-                select_k<KMAX>(C, P.K, ia, da);
+                sf_knn<KMAX>(P.M, P.invM, SfTable{P.tab_o}, qo, P.zone_o[ko], P.K, ia, da);
             }
             {
-                Cand9 C;
                 const int kd = sf_zone(P.N, qd.z);
-                sf_nearest(P.N, P.invN, SfTable{P.tab_d}, qd, kd, P.zone_d[kd], C);
-                select_k<KMAX>(C, P.K, jb, db);
+                sf_knn<KMAX>(P.N, P.invN, SfTable{P.tab_d}, qd, P.zone_d[kd], P.K, jb, db);
             }
             if constexpr (!L2) {
                 const float* g = P.img + 3 * pix;
@@ -451,13 +448,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     int ia[KMAX], jb[KMAX];
     float da[KMAX], db[KMAX];
     {
-        Cand9 Co, Cd;
         const int ko = sf_zone(P.M, qo.z), kd = sf_zone(P.N, qd.z);
-        bool conv_o, conv_d;
-        sf_nearest_pair(P.M, P.invM, SfTable{P.tab_o}, qo, ko, zb[ko], Co, P.N, P.invN, SfTable{P.tab_d}, qd, kd,
-                        zb[kZones + kd], Cd, conv_o, conv_d);
-        select_k<KMAX>(Co, P.K, ia, da, conv_o);
-        select_k<KMAX>(Cd, P.K, jb, db, conv_d);
+        sf_knn_pair<KMAX>(P.K, P.M, P.invM, SfTable{P.tab_o}, qo, zb[ko], ia, da, P.N, P.invN, SfTable{P.tab_d}, qd,
+                          zb[kZones + kd], jb, db);
     }
     if (P.nn) {
         P.nn[2 * pix] = ia[0];
@@ -484,77 +477,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
         wb[a] = jb[a] >= 0 ? tent_weight_big(db[a], P.inv_rN) : 0.0f;
     }
     f3 acc = mk3(0.0f, 0.0f, 0.0f);
-    if constexpr (FAST) {
-        // Texel addresses: a 32-bit byte offset from the field's base, origin
-        // row a at ai * row_bytes plus direction column c at co[c]; uncovered
-        // or missing neighbours read texel 0 (weight 0), so every gather is in
-        // range.
-        constexpr uint32_t TB = texel_bytes<DT>();
-        const char* const lf = (const char*)P.lf;
-        const uint32_t row_bytes = (uint32_t)P.N * TB;
-        uint32_t co[KMAX];
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c) co[c] = (uint32_t)max(jb[c], 0) * TB;
-        auto load_row = [&](int a, f3* row) {
-            const uint32_t ro = ((ia[a] >= 0 && ia[a] < P.orows) ? (uint32_t)ia[a] : 0u) * row_bytes;
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) row[c] = load_texel_at<DT>(lf + (ro + co[c]));
-        };
-        // A pair (a, c) is degenerate when origin and direction neighbour are
-        // the same point of one set (M = N).  That point lies within sqrt(da[a])
-        // of qo and sqrt(db[c]) of qd, so |qo - qd|^2 <= (sqrt(da) + sqrt(db))^2
-        // <= 2 (da + db); with a 10 % margin over the FP32 roundings, a chord
-        // longer than that rules every pair out, and the wave blends without
-        // the per-pair test.  The arithmetic is that of the plain form either
-        // way (each product rounded, then added, in the same order).
-        bool maybe_bad = false;
-        if (P.degenerate) {
-            float ma = 0.0f, mb = 0.0f;
-#pragma unroll
-            for (int a = 0; a < KMAX; ++a) {
-                ma = ia[a] >= 0 ? fmaxf(ma, da[a]) : ma;
-                mb = jb[a] >= 0 ? fmaxf(mb, db[a]) : mb;
-            }
-            maybe_bad = !(dq2 > 2.2f * (ma + mb));
-        }
-        const bool fast = __ballot(maybe_bad) == 0;  // wave-uniform
-        float wsum = 0.0f;
-        {
-            // no fused multiply-add here: the plain form's select keeps the
-            // product and the sum apart
-#pragma clang fp contract(off)
-            if (fast) {
-#pragma unroll
-                for (int a = 0; a < KMAX; ++a)
-#pragma unroll
-                    for (int c = 0; c < KMAX; ++c) wsum += wa[a] * wb[c];
-            } else {
-#pragma unroll
-                for (int a = 0; a < KMAX; ++a)
-#pragma unroll
-                    for (int c = 0; c < KMAX; ++c) wsum += ia[a] == jb[c] ? 0.0f : wa[a] * wb[c];
-            }
-        }
-        if (wsum > 0.0f) {
-            const float inv = 1.0f / wsum;
-            // origin rows in turn, the next row's loads in flight while a row is
-            // blended (two rows of texels held)
-            f3 row[2][KMAX];
-            load_row(0, row[0]);
-#pragma unroll
-            for (int a = 0; a < KMAX; ++a) {
-                if (a + 1 < KMAX) load_row(a + 1, row[(a + 1) & 1]);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int c = 0; c < KMAX; ++c) {
-                    const float w = wa[a] * wb[c] * inv;
-                    acc = fma3(row[a & 1][c], (fast || ia[a] != jb[c]) ? w : 0.0f, acc);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-    } else {
-        // plain form: every pair tested, the compiler's own load order
+    // plain form: every pair tested, the compiler's own load order
+    auto blend_plain = [&]() {
         float wsum = 0.0f;
 #pragma unroll
         for (int a = 0; a < KMAX; ++a)
@@ -576,6 +500,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
                     acc = fma3(load_texel<DT>(P.lf, t), w, acc);
                 }
         }
+    };
+    if constexpr (FAST) {
+        // A pair (a, c) is degenerate when origin and direction neighbour are
+        // the same point of one set (M = N).  That point lies within sqrt(da[a])
+        // of qo and sqrt(db[c]) of qd, so |qo - qd|^2 <= (sqrt(da) + sqrt(db))^2
+        // <= 2 (da + db); with a 10 % margin over the FP32 roundings, a chord
+        // longer than that rules every pair out.  The selection leaves the
+        // distances in ascending order (invalid entries last, at FLT_MAX or
+        // beyond K), so the last one bounds every valid one.  A wave whose
+        // pixels all pass takes the short blend, which has no per-pair test;
+        // any other wave takes the plain form.  The arithmetic is the same
+        // either way (each product rounded, then added, in the same order).
+        const bool maybe_bad = P.degenerate && !(dq2 > 2.2f * (da[KMAX - 1] + db[KMAX - 1]));
+        if (__ballot(maybe_bad) == 0) {  // wave-uniform
+            // Texel addresses: a 32-bit byte offset from the field's base,
+            // origin row a at ai * row_bytes plus direction column c at co[c];
+            // uncovered or missing neighbours read texel 0 (weight 0), so every
+            // gather is in range.
+            constexpr uint32_t TB = texel_bytes<DT>();
+            const char* const lf = (const char*)P.lf;
+            const uint32_t row_bytes = (uint32_t)P.N * TB;
+            // (24-bit multiplies: indices below 2^16, rows below 2^24 bytes,
+            // products below 2^32)
+            uint32_t co[KMAX];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) co[c] = __umul24((uint32_t)max(jb[c], 0), TB);
+            auto load_row = [&](int a, f3* row) {
+                const uint32_t ro = __umul24((ia[a] >= 0 && ia[a] < P.orows) ? (uint32_t)ia[a] : 0u, row_bytes);
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) row[c] = load_texel_at<DT>(lf + (ro + co[c]));
+            };
+            float wsum = 0.0f;
+            {
+                // no fused multiply-add here: the plain form's select keeps the
+                // product and the sum apart
+#pragma clang fp contract(off)
+#pragma unroll
+                for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) wsum += wa[a] * wb[c];
+            }
+            if (wsum > 0.0f) {
+                const float inv = 1.0f / wsum;
+                // origin rows in turn, the next row's loads in flight while a
+                // row is blended (two rows of texels held)
+                f3 row[2][KMAX];
+                load_row(0, row[0]);
+#pragma unroll
+                for (int a = 0; a < KMAX; ++a) {
+                    if (a + 1 < KMAX) load_row(a + 1, row[(a + 1) & 1]);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) acc = fma3(row[a & 1][c], wa[a] * wb[c] * inv, acc);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        } else {
+            blend_plain();
+        }
+    } else {
+        blend_plain();
     }
     float* o = P.img + 3 * pix;
     o[0] = acc.x;
@@ -681,12 +666,10 @@ __global__ void query_kernel(int n, float inv_n, float inv_r, const float* query
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
     const f3 v = normalize(mk3(query[3 * q], query[3 * q + 1], query[3 * q + 2]));
-    Cand9 C;
     const int k = sf_zone(n, v.z);
-    sf_nearest(n, inv_n, SfEval{n, inv_n}, v, k, sf_zone_basis(k, inv_n), C);
     int id[KMAX];
     float d2[KMAX];
-    select_k<KMAX>(C, K, id, d2);
+    sf_knn<KMAX>(n, inv_n, SfEval{n, inv_n}, v, sf_zone_basis(k, inv_n), K, id, d2);
 #pragma unroll
     for (int a = 0; a < KMAX; ++a) {
         if (a >= K) break;

@@ -8,7 +8,7 @@ import re
 
 import numpy as np
 
-HDR = os.path.join(os.path.dirname(__file__), "..", "paper_1903_03837_amd", "csrc", "sf_device.hpp")
+HDR = os.path.join(os.path.dirname(__file__), "..", "paper_1903_03837_amd", "csrc", "sf_search.hpp")
 
 
 def network(name="kSel5of9"):
