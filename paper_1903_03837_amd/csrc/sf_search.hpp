@@ -354,32 +354,87 @@ __device__ __forceinline__ float tent_weight_big(float d2, float inv_r) {
 // is not centred descends and selects again.
 // ---------------------------------------------------------------------------
 
-// Selection over a set assumed centred on its nearest candidate.  Returns
-// whether it is; best is the set's nearest candidate either way.  out_idx
-// and out_d2 hold select_k's result only when it returns true.
+// 32-bit keys for the selection over a first set: the squared distance's
+// bits with the low four replaced by the candidate's slot t (0..8).  The
+// keys order like the distances rounded down to 20 significant bits, ties
+// broken by slot (the centre, slot 0, first); an invalid candidate
+// (d2 = FLT_MAX) keys above every valid one.  Rounding a squared distance
+// down by at most 2^-19 of itself moves a tent weight by below 1e-6, and a
+// decision only between candidates whose distances agree to that
+// precision.  A compare-exchange is one unsigned minimum and one maximum,
+// where the 64-bit (distance, index) keys of select_k take two 64-bit
+// compares and four selects.
+constexpr uint32_t kInvalidKey = 0x7f7ffff0u;  // FLT_MAX's bits, slot field cleared
+__device__ __forceinline__ uint32_t slot_key(float d2, int t) { return (__float_as_uint(d2) & ~15u) | (uint32_t)t; }
+// Index of slot t of the set centred on c (offsets 0, +-F(k-1), +-F(k),
+// +-F(k+1), +-F(k+2) in slot order) as c + a F(k-1) + b F(k): F(k+1) =
+// F(k-1) + F(k) and F(k+2) = F(k-1) + 2 F(k).  a and b per slot are 2- and
+// 3-bit signed fields of two constants (a: 0 1 -1 0 0 1 -1 1 -1; b: 0 0 0
+// 1 -1 1 -1 2 -2), extracted by a signed bit-field extract; a host test
+// checks the constants against the offsets.
+constexpr int kSlotA[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+constexpr int kSlotB[9] = {0, 0, 0, 1, -1, 1, -1, 2, -2};
+constexpr uint32_t pack_fields(const int* v, int bits) {
+    uint32_t r = 0;
+    for (int t = 0; t < 9; ++t) r |= ((uint32_t)v[t] & ((1u << bits) - 1u)) << (bits * t);
+    return r;
+}
+constexpr uint32_t kSlotAF = pack_fields(kSlotA, 2), kSlotBF = pack_fields(kSlotB, 3);
+__device__ __forceinline__ int slot_index(int c, uint32_t t, int f_km1, int f_k) {
+    const int a = __builtin_amdgcn_sbfe((int)kSlotAF, 2 * t, 2);
+    const int b = __builtin_amdgcn_sbfe((int)kSlotBF, 3 * t, 3);
+    return c + __mul24(a, f_km1) + __mul24(b, f_k);
+}
+
+// Selection over a first set, centred on c, assumed centred on its nearest
+// candidate.  Returns whether it is; best is the set's nearest candidate
+// either way.  out_idx and out_d2 hold the K nearest (out_d2 rounded down as
+// above for K <= 5) only when it returns true.
 template <int KMAX>
-__device__ __forceinline__ bool select_k_centred(const Cand9& C, int K, int* out_idx, float* out_d2, int& best) {
-    uint64_t key[9];
-    cand_keys(C, key);
-    uint64_t least;  // the smallest key of the nine
-    if constexpr (KMAX == 1) {
-        uint64_t m = key[1];
+__device__ __forceinline__ bool select_k_centred(const Cand9& C, const SfZone& Z, int c, int K, int* out_idx,
+                                                 float* out_d2, int& best) {
+    if constexpr (KMAX <= 5) {
+        uint32_t key[9];
 #pragma unroll
-        for (int a = 2; a < 9; ++a) m = key[a] < m ? key[a] : m;
-        least = key[0] < m ? key[0] : m;
-    } else if constexpr (KMAX <= 5) {
-        // the network over candidates 1..8 leaves their smallest in position 1
+        for (int t = 0; t < 9; ++t) key[t] = slot_key(C.d2[t], t);
+        if constexpr (KMAX == 1) {
+            uint32_t m = key[1];
 #pragma unroll
-        for (int c = 0; c < kSel4of8; ++c) {
-            const int a = kSel4of8Net[c][0] + 1, b = kSel4of8Net[c][1] + 1;
-            const uint64_t lo = key[a] < key[b] ? key[a] : key[b];
-            const uint64_t hi = key[a] < key[b] ? key[b] : key[a];
-            key[a] = lo;
-            key[b] = hi;
+            for (int a = 2; a < 9; ++a) m = min(m, key[a]);
+            key[1] = m;
+        } else {
+            // the network over candidates 1..8 leaves their four smallest in
+            // positions 1..4, in order
+#pragma unroll
+            for (int e = 0; e < kSel4of8; ++e) {
+                const int a = kSel4of8Net[e][0] + 1, b = kSel4of8Net[e][1] + 1;
+                const uint32_t lo = min(key[a], key[b]), hi = max(key[a], key[b]);
+                key[a] = lo;
+                key[b] = hi;
+            }
         }
-        least = key[0] < key[1] ? key[0] : key[1];
+        // (the Fibonacci steps read once: decoded indices are plain
+        // arithmetic, which the compiler keeps out of branches)
+        const int f_km1 = Z.f_km1, f_k = Z.f_k;
+        int id[KMAX];
+#pragma unroll
+        for (int r = 1; r < KMAX; ++r) id[r] = slot_index(c, key[r] & 15u, f_km1, f_k);
+        const bool centred = key[0] < key[1];
+        best = centred ? c : (KMAX > 1 ? id[1] : slot_index(c, key[1] & 15u, f_km1, f_k));
+        // the centre first, then the smallest of the others
+        out_idx[0] = c;  // (K >= 1 and the centre is a valid candidate)
+        out_d2[0] = __uint_as_float(key[0] & ~15u);
+#pragma unroll
+        for (int r = 1; r < KMAX; ++r) {
+            const bool ok = r < K && key[r] < kInvalidKey;
+            out_idx[r] = ok ? id[r] : -1;
+            out_d2[r] = __uint_as_float(key[r] & ~15u);
+        }
+        return centred;
     } else {
-        // all nine sorted (select_k ignores centre_min here)
+        // all nine sorted on the 64-bit keys (select_k ignores centre_min here)
+        uint64_t key[9];
+        cand_keys(C, key);
 #pragma unroll
         for (int p = 0; p < 9; ++p)
 #pragma unroll
@@ -389,11 +444,10 @@ __device__ __forceinline__ bool select_k_centred(const Cand9& C, int K, int* out
                 key[a] = lo;
                 key[a + 1] = hi;
             }
-        least = key[0];
+        best = (int)(uint32_t)key[0];
+        keys_out<KMAX>(key, K, out_idx, out_d2);
+        return best == C.idx[0];
     }
-    best = (int)(uint32_t)least;
-    keys_out<KMAX>(key, K, out_idx, out_d2);
-    return best == C.idx[0];
 }
 
 // The descent from a first set centred on c whose nearest candidate is
@@ -427,7 +481,7 @@ __device__ __forceinline__ void sf_knn(int n, float inv_n, const Pts& pts, f3 q,
     if (__ballot(!lat) == 0) sf_candidates_at_corner(n, pts, q, Z, c, s, cd, C);  // wave-uniform
     else sf_candidates(n, pts, q, Z, c, C);
     int best;
-    if (!select_k_centred<KMAX>(C, K, out_idx, out_d2, best))
+    if (!select_k_centred<KMAX>(C, Z, c, K, out_idx, out_d2, best))
         sf_descend_select<KMAX>(n, pts, q, Z, c, best, K, out_idx, out_d2);
 }
 
@@ -456,8 +510,8 @@ __device__ __forceinline__ void sf_knn_pair(int K, int n1, float inv1, const Pts
     // than the loaded points of one set held across the other's selection)
     __builtin_amdgcn_sched_barrier(0);
     int b1, b2;
-    const bool ok1 = select_k_centred<KMAX>(C1, K, i1, d1, b1);
-    const bool ok2 = select_k_centred<KMAX>(C2, K, i2, d2, b2);
+    const bool ok1 = select_k_centred<KMAX>(C1, Z1, c1, K, i1, d1, b1);
+    const bool ok2 = select_k_centred<KMAX>(C2, Z2, c2, K, i2, d2, b2);
     if (!ok1) sf_descend_select<KMAX>(n1, p1, q1, Z1, c1, b1, K, i1, d1);
     if (!ok2) sf_descend_select<KMAX>(n2, p2, q2, Z2, c2, b2, K, i2, d2);
 }

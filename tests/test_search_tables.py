@@ -90,3 +90,58 @@ def test_corner_slots_reach_the_other_corners():
             for s2 in range(4):
                 assert off[corner[s][s2]] == pos(s2) - pos(s), (k, s, s2)
             assert sorted(corner[s] + opens[s]) == list(range(9)), s
+
+
+def slot_fields():
+    a = [int(v) for v in re.search(r"kSlotA\[9\] = \{([^}]*)\}", SRC).group(1).split(",")]
+    b = [int(v) for v in re.search(r"kSlotB\[9\] = \{([^}]*)\}", SRC).group(1).split(",")]
+    return a, b
+
+
+def test_slot_decode_gives_the_candidate_offsets():
+    """slot t of a candidate set lies at a(t) F(k-1) + b(t) F(k) from its
+    centre; a and b fit the 2- and 3-bit signed fields they are packed in"""
+    a, b = slot_fields()
+    assert len(a) == len(b) == 9
+    assert all(-2 <= v <= 1 for v in a) and all(-4 <= v <= 3 for v in b)
+    for k in range(2, 21):
+        f1, f2, f3, f4 = fib(k - 1), fib(k), fib(k + 1), fib(k + 2)
+        off = [0, f1, -f1, f2, -f2, f3, -f3, f4, -f4]
+        assert [a[t] * f1 + b[t] * f2 for t in range(9)] == off, k
+
+
+def test_slot_fields_round_trip_through_the_packing():
+    """the packed constants, extracted as signed bit fields, give a and b back"""
+    a, b = slot_fields()
+
+    def pack(v, bits):
+        return sum((x & ((1 << bits) - 1)) << (bits * t) for t, x in enumerate(v))
+
+    def sbfe(word, off, bits):
+        x = (word >> off) & ((1 << bits) - 1)
+        return x - (1 << bits) if x >> (bits - 1) else x
+
+    pa, pb = pack(a, 2), pack(b, 3)
+    assert pa < 2 ** 31 and pb < 2 ** 31  # the device reads them as int
+    assert [sbfe(pa, 2 * t, 2) for t in range(9)] == a
+    assert [sbfe(pb, 3 * t, 3) for t in range(9)] == b
+
+
+def test_slot_keys_order_like_distances():
+    """32-bit keys (distance bits with the slot in the low four) order valid
+    candidates by distance rounded down to 20 significant bits, ties by slot,
+    and every invalid candidate (FLT_MAX) after every valid one"""
+    inv = int(re.search(r"kInvalidKey = (0x[0-9a-f]+)u", SRC).group(1), 16)
+    rng = np.random.default_rng(4)
+    d2 = rng.uniform(0, 4, (20000, 9)).astype(np.float32)
+    bits = d2.view(np.uint32)
+    keys = (bits & ~np.uint32(15)) | np.arange(9, dtype=np.uint32)
+    assert keys.max() < inv
+    fmax = np.float32(np.finfo(np.float32).max).view(np.uint32)
+    assert (fmax & ~np.uint32(15)) == inv
+    order = np.argsort(keys, 1)
+    trunc = (bits & ~np.uint32(15)).view(np.float32)
+    srt = np.take_along_axis(trunc, order, 1)
+    assert np.all(np.diff(srt, axis=1) >= 0)
+    # rounding down loses at most 2^-19 of the value
+    assert np.all((d2 - trunc) <= d2 * 2.0 ** -19)
