@@ -77,6 +77,96 @@ __device__ __forceinline__ void sort_by_index(int* idx, float* w) {
         }
 }
 
+// The pixel's view ray and its front and back hits on the unit sphere S,
+// with the same arithmetic in every lookup kernel, so that the forward
+// lookup, the fused lookup + loss and the transpose weigh the same
+// neighbours by the same weights.  Square roots, normalisations and
+// divisions use the hardware square root, reciprocal square root and
+// reciprocal (v_sqrt_f32, v_rsq_f32, v_rcp_f32, about an ulp each; 1-2
+// instructions where a correctly rounded square root or an IEEE division
+// takes ~10): a hit moves by a few 1e-7 of the radius either way.  Returns false for a ray that misses S or grazes
+// it (discriminant at most thr).
+__device__ __forceinline__ f3 normalize_rsq(f3 a) { return a * __builtin_amdgcn_rsqf(dot(a, a)); }
+__device__ __forceinline__ bool view_hits(const LookupParams& P, const ViewGeom& G, int px, int py, f3& qo, f3& qd) {
+    const float ndx = (2.0f * ((float)px + 0.5f) * __builtin_amdgcn_rcpf((float)P.W) - 1.0f) * G.sx;
+    const float ndy = (1.0f - 2.0f * ((float)py + 0.5f) * __builtin_amdgcn_rcpf((float)P.H)) * G.sy;
+    const f3 d = normalize_rsq(mk3(G.fwd[0], G.fwd[1], G.fwd[2]) + mk3(G.right[0], G.right[1], G.right[2]) * ndx +
+                               mk3(G.up[0], G.up[1], G.up[2]) * ndy);
+    const f3 oc = mk3(G.oc[0], G.oc[1], G.oc[2]);
+    const float b = dot(d, oc);
+    const float disc = b * b - G.c;
+    if (!(disc > P.thr)) return false;
+    const float sq = __builtin_amdgcn_sqrtf(disc);
+    qo = normalize_rsq(fma3(d, -b - sq, oc));
+    qd = normalize_rsq(fma3(d, -b + sq, oc));
+    return true;
+}
+// 1 / (sum of a pixel's pair weights), positive and normal, by the hardware
+// reciprocal.
+__device__ __forceinline__ float inv_weight_sum(float wsum) { return __builtin_amdgcn_rcpf(wsum); }
+// Tent weight of a neighbour at squared chord d2 (filter radius 1 / inv_r),
+// with the hardware square root.
+__device__ __forceinline__ float tent_weight_hw(float d2, float inv_r) {
+    return fmaxf(0.0f, 1.0f - __builtin_amdgcn_sqrtf(d2) * inv_r);
+}
+
+// Separable blend.  When no pair (a, c) of a pixel is degenerate (origin
+// and direction neighbour the same point of one set), its pair weights are
+// the products wa[a] wb[c], so the weight sum is (sum wa)(sum wb) and the
+// view is sum_a wa[a] (sum_c wb[c] T[a][c]) / that sum: 3 multiply-adds per
+// texel and 3 per row, against a product, a scaled product and 3
+// multiply-adds per texel and a product and a sum per pair for the
+// per-pair form.  A pair's point would lie within sqrt(da) of q_o and
+// sqrt(db) of q_d, so |q_o - q_d|^2 <= 2 (da + db); with a 10 % margin
+// over the FP32 roundings, a chord above 2.2 (da + db) of the farthest kept
+// neighbours (the selection leaves distances in ascending order, invalid
+// entries last) rules every pair out.  The decision is taken per wave (a
+// ballot over the lanes with a pixel on S), in the same way in the forward
+// lookup and the fused lookup + loss, so both form each view value with
+// the same arithmetic.
+// The light field (stored origin rows x N texels of its storage type)
+// spans at most 4 GiB.
+__host__ __device__ inline bool field_within_4gib(const LookupParams& P) {
+    return (uint64_t)P.orows * (uint64_t)P.N * (uint64_t)(P.dtype == 0 ? 12 : 6) <= (1ull << 32);
+}
+template <int KMAX>
+__device__ __forceinline__ bool separable_wave(const LookupParams& P, f3 qo, f3 qd, const float* da, const float* db) {
+    const bool maybe_bad = P.degenerate && !(dist2(qo, qd) > 2.2f * (da[KMAX - 1] + db[KMAX - 1]));
+    return __ballot(maybe_bad) == 0;
+}
+template <int KMAX>
+__device__ __forceinline__ float separable_weight_sum(const float* wa, const float* wb) {
+    float sa = 0.0f, sb = 0.0f;
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a) {
+        sa += wa[a];
+        sb += wb[a];
+    }
+    return sa * sb;
+}
+// Per-pair weight sum: degenerate pairs left out when the sets are one.
+template <int KMAX>
+__device__ __forceinline__ float pair_weight_sum(const LookupParams& P, const int* ia, const float* wa, const int* jb,
+                                                 const float* wb) {
+    float wsum = 0.0f;
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) {
+            const bool bad = P.degenerate && ia[a] == jb[c];
+            wsum += bad ? 0.0f : wa[a] * wb[c];
+        }
+    return wsum;
+}
+// One origin row of the separable blend: acc += wa (sum_c wb[c] T[c]).
+template <int KMAX>
+__device__ __forceinline__ f3 blend_row(const f3* T, const float* wb, float wa, f3 acc) {
+    f3 r = mk3(0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) r = fma3(T[c], wb[c], r);
+    return fma3(r, wa, acc);
+}
+
 // DPP lane move (a v_mov_b32_dpp): lanes that the row / bank masks disable,
 // or whose source lies outside the row under bound_ctrl, read `old`.
 template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_CTRL>
@@ -282,17 +372,8 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
     if (live) {
         const ViewGeom& G = P.v[v];
         const uint64_t pix = ((uint64_t)(P.view0 + v) * P.H + py) * P.W + px;
-        const float ndx = (2.0f * ((float)px + 0.5f) / (float)P.W - 1.0f) * G.sx;
-        const float ndy = (1.0f - 2.0f * ((float)py + 0.5f) / (float)P.H) * G.sy;
-        const f3 d = normalize(mk3(G.fwd[0], G.fwd[1], G.fwd[2]) + mk3(G.right[0], G.right[1], G.right[2]) * ndx +
-                               mk3(G.up[0], G.up[1], G.up[2]) * ndy);
-        const f3 oc = mk3(G.oc[0], G.oc[1], G.oc[2]);
-        const float b = dot(d, oc);
-        const float disc = b * b - G.c;
-        if (disc > P.thr) {
-            const float sq = sqrtf(disc);
-            const f3 qo = normalize(fma3(d, -b - sq, oc));
-            const f3 qd = normalize(fma3(d, -b + sq, oc));
+        f3 qo, qd;
+        if (view_hits(P, G, px, py, qo, qd)) {
             float da[KMAX], db[KMAX];
             // (one search after the other: the scatter's registers leave no room
             // for both searches' candidate sets at once)
@@ -318,32 +399,47 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
                     gi = covered ? load_texel<DT>(P.lf, t) : mk3(0.0f, 0.0f, 0.0f);
                 }
             } else {
-                float wsum = 0.0f;
 #pragma unroll
                 for (int a = 0; a < KMAX; ++a) {
-                    wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight(da[a], P.inv_rM) : 0.0f;
-                    wb[a] = jb[a] >= 0 ? tent_weight(db[a], P.inv_rN) : 0.0f;
+                    wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight_hw(da[a], P.inv_rM) : 0.0f;
+                    wb[a] = jb[a] >= 0 ? tent_weight_hw(db[a], P.inv_rN) : 0.0f;
                 }
-#pragma unroll
-                for (int a = 0; a < KMAX; ++a)
-#pragma unroll
-                    for (int c = 0; c < KMAX; ++c)
-                        wsum += (P.degenerate && ia[a] == jb[c]) ? 0.0f : wa[a] * wb[c];
-                inv = wsum > 0.0f ? 1.0f / wsum : 0.0f;
+                // the forward's weight sum and blend, term for term in the
+                // same order (separable for five neighbours when the wave
+                // has no degenerate pair)
+                bool sep = false;
+                if constexpr (KMAX == 5) sep = field_within_4gib(P) && separable_wave<KMAX>(P, qo, qd, da, db);
+                const float wsum = sep ? separable_weight_sum<KMAX>(wa, wb) : pair_weight_sum<KMAX>(P, ia, wa, jb, wb);
+                inv = wsum > 0.0f ? inv_weight_sum(wsum) : 0.0f;
                 if constexpr (L2) {
-                    // the forward's blend, term for term in the same order
                     f3 acc = mk3(0.0f, 0.0f, 0.0f);
                     if (wsum > 0.0f) {
+                        if (sep) {
+                            // (blend_row's arithmetic, a texel loaded per step:
+                            // fewer live registers in this kernel)
 #pragma unroll
-                        for (int a = 0; a < KMAX; ++a)
-#pragma unroll
-                            for (int c = 0; c < KMAX; ++c) {
-                                const bool bad = P.degenerate && ia[a] == jb[c];
-                                const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
+                            for (int a = 0; a < KMAX; ++a) {
                                 const int ai = (ia[a] >= 0 && ia[a] < P.orows) ? ia[a] : 0;
-                                const uint64_t t = (uint64_t)ai * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
-                                acc = fma3(load_texel<DT>(P.lf, t), w, acc);
+                                f3 r = mk3(0.0f, 0.0f, 0.0f);
+#pragma unroll
+                                for (int c = 0; c < KMAX; ++c)
+                                    r = fma3(load_texel<DT>(P.lf, (uint64_t)ai * (uint64_t)P.N + (uint64_t)max(jb[c], 0)),
+                                             wb[c], r);
+                                acc = fma3(r, wa[a], acc);
                             }
+                            acc = acc * inv;
+                        } else {
+#pragma unroll
+                            for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+                                for (int c = 0; c < KMAX; ++c) {
+                                    const bool bad = P.degenerate && ia[a] == jb[c];
+                                    const float w = bad ? 0.0f : wa[a] * wb[c] * inv;
+                                    const int ai = (ia[a] >= 0 && ia[a] < P.orows) ? ia[a] : 0;
+                                    const uint64_t t = (uint64_t)ai * (uint64_t)P.N + (uint64_t)max(jb[c], 0);
+                                    acc = fma3(load_texel<DT>(P.lf, t), w, acc);
+                                }
+                        }
                     }
                     gi = acc;
                 }
@@ -394,19 +490,20 @@ __global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) 
     lookup_adjoint_pixel<KMAX, DT, L2>(P, lds[wave], px, py, blockIdx.z);
 }
 
-// Bound by VALU issue (the searches, the selection and the blend) while the
-// field stays in the caches; on a field of many GB the gathers' misses to
-// HBM take their share too.  K <= 5 is held to 6 waves per SIMD (no
-// spills), which 7 or 8 waves do not beat.
-// OFF32: the field spans at most 4 GiB, so a texel is addressed by a 32-bit
-// byte offset from the field's (uniform) base, one add per texel.
+// Bound by VALU issue (the searches, the selection and the blend) and the
+// gathers' latency while the field stays in the caches; on a field of many
+// GB the gathers' misses to HBM take their share too.  K <= 5 is held to 7
+// waves per SIMD on fields within 4 GiB (72 VGPRs) and 6 on larger ones
+// (80: the per-pair blend holds more texels), K = 9 to 3.
+// OFF32: the field spans at most 4 GiB (field_within_4gib), so a texel is
+// addressed by a 32-bit byte offset from the field's (uniform) base, one add
+// per texel; there five neighbours blend separably in a wave without
+// degenerate pairs, by pairs otherwise.  K = 9 and larger fields blend by
+// pairs (on a field of many GB, whose gathers miss to HBM, the compiler's
+// own load order beats the row-ahead loads).
 template <int KMAX, int DT, bool OFF32>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ? 6 : 1))) void lookup_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ? (OFF32 ? 7 : 6) : 3))) void lookup_kernel(
     LookupParams P) {
-    // the short blend (fewer VALU instructions, more registers) pays for five
-    // neighbours in a field below 4 GiB; K = 1, K = 9 and larger fields keep
-    // the plain form
-    constexpr bool FAST = KMAX == 5 && OFF32;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
@@ -418,18 +515,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     if (px >= P.W || py >= P.H) return;
     const ViewGeom& G = P.v[v];
     const uint64_t pix = ((uint64_t)(P.view0 + v) * P.H + py) * P.W + px;
-    const float ndx = (2.0f * ((float)px + 0.5f) / (float)P.W - 1.0f) * G.sx;
-    const float ndy = (1.0f - 2.0f * ((float)py + 0.5f) / (float)P.H) * G.sy;
-    const f3 fwd = mk3(G.fwd[0], G.fwd[1], G.fwd[2]);
-    const f3 rt = mk3(G.right[0], G.right[1], G.right[2]);
-    const f3 up = mk3(G.up[0], G.up[1], G.up[2]);
-    // (squared lengths: the view ray's is at least 1, the hits' about R^2, and
-    // disc exceeds 1e-6 R^2, so the short correctly rounded square root applies)
-    const f3 d = normalize_big(fwd + rt * ndx + up * ndy);
-    const f3 oc = mk3(G.oc[0], G.oc[1], G.oc[2]);
-    const float b = dot(d, oc);
-    const float disc = b * b - G.c;
-    if (!(disc > P.thr)) {
+    f3 qo, qd;
+    if (!view_hits(P, G, px, py, qo, qd)) {
         {
             float* o = P.img + 3 * pix;
             o[0] = o[1] = o[2] = 0.0f;
@@ -440,10 +527,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
         }
         return;
     }
-    const float sq = sqrt_big(disc);
-    const f3 qo = normalize_big(fma3(d, -b - sq, oc));
-    const f3 qd = normalize_big(fma3(d, -b + sq, oc));
-    const float dq2 = dist2(qo, qd);  // squared chord between the hits
 
     int ia[KMAX], jb[KMAX];
     float da[KMAX], db[KMAX];
@@ -473,22 +556,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
     float wa[KMAX], wb[KMAX];
 #pragma unroll
     for (int a = 0; a < KMAX; ++a) {
-        wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight_big(da[a], P.inv_rM) : 0.0f;
-        wb[a] = jb[a] >= 0 ? tent_weight_big(db[a], P.inv_rN) : 0.0f;
+        wa[a] = (ia[a] >= 0 && ia[a] < P.orows) ? tent_weight_hw(da[a], P.inv_rM) : 0.0f;
+        wb[a] = jb[a] >= 0 ? tent_weight_hw(db[a], P.inv_rN) : 0.0f;
     }
     f3 acc = mk3(0.0f, 0.0f, 0.0f);
-    // plain form: every pair tested, the compiler's own load order
-    auto blend_plain = [&]() {
-        float wsum = 0.0f;
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a)
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) {
-                const bool bad = P.degenerate && ia[a] == jb[c];
-                wsum += bad ? 0.0f : wa[a] * wb[c];
-            }
+    // per-pair form: every pair tested, the compiler's own load order
+    auto blend_pairs = [&]() {
+        const float wsum = pair_weight_sum<KMAX>(P, ia, wa, jb, wb);
         if (wsum > 0.0f) {
-            const float inv = 1.0f / wsum;
+            const float inv = inv_weight_sum(wsum);
 #pragma unroll
             for (int a = 0; a < KMAX; ++a)
 #pragma unroll
@@ -501,48 +577,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
                 }
         }
     };
-    if constexpr (FAST) {
-        // A pair (a, c) is degenerate when origin and direction neighbour are
-        // the same point of one set (M = N).  That point lies within sqrt(da[a])
-        // of qo and sqrt(db[c]) of qd, so |qo - qd|^2 <= (sqrt(da) + sqrt(db))^2
-        // <= 2 (da + db); with a 10 % margin over the FP32 roundings, a chord
-        // longer than that rules every pair out.  The selection leaves the
-        // distances in ascending order (invalid entries last, at FLT_MAX or
-        // beyond K), so the last one bounds every valid one.  A wave whose
-        // pixels all pass takes the short blend, which has no per-pair test;
-        // any other wave takes the plain form.  The arithmetic is the same
-        // either way (each product rounded, then added, in the same order).
-        const bool maybe_bad = P.degenerate && !(dq2 > 2.2f * (da[KMAX - 1] + db[KMAX - 1]));
-        if (__ballot(maybe_bad) == 0) {  // wave-uniform
-            // Texel addresses: a 32-bit byte offset from the field's base,
-            // origin row a at ai * row_bytes plus direction column c at co[c];
-            // uncovered or missing neighbours read texel 0 (weight 0), so every
-            // gather is in range.
-            constexpr uint32_t TB = texel_bytes<DT>();
-            const char* const lf = (const char*)P.lf;
-            const uint32_t row_bytes = (uint32_t)P.N * TB;
-            // (24-bit multiplies: indices below 2^16, rows below 2^24 bytes,
-            // products below 2^32)
-            uint32_t co[KMAX];
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) co[c] = __umul24((uint32_t)max(jb[c], 0), TB);
-            auto load_row = [&](int a, f3* row) {
-                const uint32_t ro = __umul24((ia[a] >= 0 && ia[a] < P.orows) ? (uint32_t)ia[a] : 0u, row_bytes);
-#pragma unroll
-                for (int c = 0; c < KMAX; ++c) row[c] = load_texel_at<DT>(lf + (ro + co[c]));
-            };
-            float wsum = 0.0f;
-            {
-                // no fused multiply-add here: the plain form's select keeps the
-                // product and the sum apart
-#pragma clang fp contract(off)
-#pragma unroll
-                for (int a = 0; a < KMAX; ++a)
-#pragma unroll
-                    for (int c = 0; c < KMAX; ++c) wsum += wa[a] * wb[c];
-            }
+    if constexpr (KMAX == 5 && OFF32) {
+        if (separable_wave<KMAX>(P, qo, qd, da, db)) {  // wave-uniform
+            const float wsum = separable_weight_sum<KMAX>(wa, wb);
             if (wsum > 0.0f) {
-                const float inv = 1.0f / wsum;
+                const float inv = inv_weight_sum(wsum);
+                // Uncovered or missing neighbours read texel 0 (weight 0), so
+                // every gather is in range.  A texel is a 32-bit byte offset
+                // from the field's base, origin row a at ai * row_bytes plus
+                // direction column c at co[c] (24-bit multiplies: indices
+                // below 2^16, rows below 2^24 bytes, products below 2^32).
+                constexpr uint32_t TB = texel_bytes<DT>();
+                const char* const lf = (const char*)P.lf;
+                const uint32_t row_bytes = (uint32_t)P.N * TB;
+                uint32_t co[KMAX];
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) co[c] = __umul24((uint32_t)max(jb[c], 0), TB);
+                auto load_row = [&](int a, f3* row) {
+                    const int ai = (ia[a] >= 0 && ia[a] < P.orows) ? ia[a] : 0;
+                    const uint32_t ro = __umul24((uint32_t)ai, row_bytes);
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) row[c] = load_texel_at<DT>(lf + (ro + co[c]));
+                };
                 // origin rows in turn, the next row's loads in flight while a
                 // row is blended (two rows of texels held)
                 f3 row[2][KMAX];
@@ -551,16 +607,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
                 for (int a = 0; a < KMAX; ++a) {
                     if (a + 1 < KMAX) load_row(a + 1, row[(a + 1) & 1]);
                     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int c = 0; c < KMAX; ++c) acc = fma3(row[a & 1][c], wa[a] * wb[c] * inv, acc);
+                    acc = blend_row<KMAX>(row[a & 1], wb, wa[a], acc);
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                acc = acc * inv;
             }
         } else {
-            blend_plain();
+            blend_pairs();
         }
     } else {
-        blend_plain();
+        blend_pairs();
     }
     float* o = P.img + 3 * pix;
     o[0] = acc.x;
@@ -571,8 +627,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
 template <int KMAX, int DT>
 static hipError_t launch_lookup_mode(const LookupParams& P, int mode, hipStream_t s) {
     dim3 grid((P.W + 15) / 16, (P.H + 15) / 16, P.nviews);
-    const bool off32 = (uint64_t)P.orows * (uint64_t)P.N * (uint64_t)texel_bytes<DT>() <= (1ull << 32);
-    if (mode == 0 && off32) lookup_kernel<KMAX, DT, true><<<grid, 256, 0, s>>>(P);
+    if (mode == 0 && field_within_4gib(P)) lookup_kernel<KMAX, DT, true><<<grid, 256, 0, s>>>(P);
     else if (mode == 0) lookup_kernel<KMAX, DT, false><<<grid, 256, 0, s>>>(P);
     else if (mode == 1) lookup_adjoint_kernel<KMAX, 0, false><<<grid, 256, 0, s>>>(P);
     else lookup_adjoint_kernel<KMAX, DT, true><<<grid, 256, 0, s>>>(P);

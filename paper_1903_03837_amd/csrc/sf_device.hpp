@@ -31,20 +31,6 @@ __device__ __forceinline__ f3 cross(f3 a, f3 b) {
 }
 __device__ __forceinline__ f3 normalize(f3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
 
-// Correctly rounded square root of x = +0 or finite x >= 2^-96: the hardware
-// square root (within 1 ulp), then its lower or upper neighbour by the sign
-// of the fma residual.  For such x this is the value sqrtf gives (sqrtf also
-// rescales inputs below 2^-96 and passes special values through, which costs
-// another seven instructions).
-__device__ __forceinline__ float sqrt_big(float x) {
-    const float s = __builtin_amdgcn_sqrtf(x);
-    const float lo = __uint_as_float(__float_as_uint(s) - 1u), hi = __uint_as_float(__float_as_uint(s) + 1u);
-    float r = fmaf(-lo, s, x) <= 0.0f ? lo : s;
-    r = fmaf(-hi, s, x) > 0.0f ? hi : r;
-    return r;
-}
-// normalize() of a vector whose squared length is at least 2^-96.
-__device__ __forceinline__ f3 normalize_big(f3 a) { return a * (1.0f / sqrt_big(dot(a, a))); }
 __device__ __forceinline__ f3 fma3(f3 a, float s, f3 b) {  // a * s + b
     return {fmaf(a.x, s, b.x), fmaf(a.y, s, b.y), fmaf(a.z, s, b.z)};
 }

@@ -14,7 +14,7 @@
 namespace lp {
 
 constexpr double kPiD = 3.14159265358979323846;
-constexpr float kInvLogPhi2 = 1.0390834931f;  // 1 / ln(Phi^2)
+constexpr float kInvLog2Phi2 = 0.72021004520627820f;  // 1 / log2(Phi^2)
 constexpr float kPiSqrt5 = 7.0248147310f;     // pi * sqrt(5)
 
 // Point sources for the inverse mapping: evaluated on the fly, or read from
@@ -40,11 +40,15 @@ __device__ __forceinline__ int fib(int k) {
     return k < 0 ? 1 : t[k];
 }
 
-// Zone number k = max(2, floor(log_{Phi^2}(n pi sqrt5 (1 - z^2)))).
+// Zone number k = max(2, floor(log_{Phi^2}(n pi sqrt5 (1 - z^2)))), with
+// the hardware base-2 logarithm (v_log_f32, about an ulp; arg is a normal
+// number or zero): the zone only picks the lattice basis, and an ulp moves
+// k only for heights within ~1e-7 of a zone boundary, where either basis
+// serves: the candidate offsets F(k-1) .. F(k+2) hold both zones' steps.
 __device__ __forceinline__ int sf_zone(int n, float qz) {
     const float arg = (float)n * kPiSqrt5 * ((1.0f - qz) * (1.0f + qz));
     if (!(arg > 0.0f)) return 2;
-    const int k = (int)floorf(logf(arg) * kInvLogPhi2);
+    const int k = (int)floorf(__builtin_amdgcn_logf(arg) * kInvLog2Phi2);
     return k < 2 ? 2 : (k > 20 ? 20 : k);
 }
 
@@ -335,11 +339,6 @@ __device__ __forceinline__ int select_k(const Cand9& C, int K, int* out_idx, flo
 // kernel of size R sqrt(4 pi / N), with R scaled out).
 __device__ __forceinline__ float tent_weight(float d2, float inv_r) {
     return fmaxf(0.0f, 1.0f - sqrtf(d2) * inv_r);
-}
-// The same weight with the short square root: a d2 below 2^-96 gives weight 1
-// with either square root (sqrt(d2) * inv_r < 2^-41 for n <= 65535).
-__device__ __forceinline__ float tent_weight_big(float d2, float inv_r) {
-    return fmaxf(0.0f, 1.0f - sqrt_big(d2) * inv_r);
 }
 
 // ---------------------------------------------------------------------------

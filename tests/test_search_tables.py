@@ -145,3 +145,12 @@ def test_slot_keys_order_like_distances():
     assert np.all(np.diff(srt, axis=1) >= 0)
     # rounding down loses at most 2^-19 of the value
     assert np.all((d2 - trunc) <= d2 * 2.0 ** -19)
+
+
+def test_zone_constants():
+    """the zone number's constants: 1 / log2(Phi^2) and pi sqrt(5)"""
+    phi = (1 + 5 ** 0.5) / 2
+    inv = float(re.search(r"kInvLog2Phi2 = ([0-9.]+)f;", SRC).group(1))
+    assert abs(inv - np.log(2) / np.log(phi * phi)) < 1e-9
+    ps5 = float(re.search(r"kPiSqrt5 = ([0-9.]+)f;", SRC).group(1))
+    assert abs(ps5 - np.pi * np.sqrt(5)) < 1e-8
