@@ -654,14 +654,17 @@ def test_lookup_adjoint_stored_rows(lp, orc, K):
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("K,dtype,rows", [(5, "f32", 0), (1, "f32", 0), (5, "f16", 0), (9, "bf16", 0),
-                                          (5, "f32", 128), (1, "f32", 128)])
-def test_lookup_l2_fused(lp, K, dtype, rows):
+@pytest.mark.parametrize("K,dtype,rows,N", [(5, "f32", 0, 256), (1, "f32", 0, 256), (5, "f16", 0, 256),
+                                            (9, "bf16", 0, 256), (5, "f32", 128, 256), (1, "f32", 128, 256),
+                                            (3, "f32", 0, 256), (5, "f32", 0, 192), (5, "bf16", 128, 320)])
+def test_lookup_l2_fused(lp, K, dtype, rows, N):
     """lf_lookup_l2 writes the forward views bit for bit and adds the
     transpose of (views - target) to d_lf, as lookup, subtraction and
     lookup_adjoint do separately (to float-atomic rounding); also with only
-    the upper-hemisphere origin rows stored."""
-    M = N = 256
+    the upper-hemisphere origin rows stored, with fewer neighbours than the
+    kernel's five slots, and with two different point sets (no degenerate
+    pairs: every wave blends separably)."""
+    M = 256
     V, W, H = 3, 96, 64
     sc = S.config(1, M=M, N=N, views=V, width=W, height=H, origin_rows=rows)
     if rows:
