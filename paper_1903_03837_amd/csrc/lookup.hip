@@ -405,10 +405,9 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
                     wb[a] = jb[a] >= 0 ? tent_weight_hw(db[a], P.inv_rN) : 0.0f;
                 }
                 // the forward's weight sum and blend, term for term in the
-                // same order (separable for five neighbours when the wave
+                // same order (separable on a field within 4 GiB when the wave
                 // has no degenerate pair)
-                bool sep = false;
-                if constexpr (KMAX == 5) sep = field_within_4gib(P) && separable_wave<KMAX>(P, qo, qd, da, db);
+                const bool sep = field_within_4gib(P) && separable_wave<KMAX>(P, qo, qd, da, db);
                 const float wsum = sep ? separable_weight_sum<KMAX>(wa, wb) : pair_weight_sum<KMAX>(P, ia, wa, jb, wb);
                 inv = wsum > 0.0f ? inv_weight_sum(wsum) : 0.0f;
                 if constexpr (L2) {
@@ -497,10 +496,10 @@ __global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) 
 // (80: the per-pair blend holds more texels), K = 9 to 3.
 // OFF32: the field spans at most 4 GiB (field_within_4gib), so a texel is
 // addressed by a 32-bit byte offset from the field's (uniform) base, one add
-// per texel; there five neighbours blend separably in a wave without
-// degenerate pairs, by pairs otherwise.  K = 9 and larger fields blend by
-// pairs (on a field of many GB, whose gathers miss to HBM, the compiler's
-// own load order beats the row-ahead loads).
+// per texel; there the neighbours blend separably in a wave without
+// degenerate pairs, by pairs otherwise.  Larger fields blend by pairs (on a
+// field of many GB, whose gathers miss to HBM, the compiler's own load
+// order beats the row-ahead loads).
 template <int KMAX, int DT, bool OFF32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ? (OFF32 ? 7 : 6) : 3))) void lookup_kernel(
     LookupParams P) {
@@ -577,7 +576,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 5 ?
                 }
         }
     };
-    if constexpr (KMAX == 5 && OFF32) {
+    if constexpr (OFF32) {
         if (separable_wave<KMAX>(P, qo, qd, da, db)) {  // wave-uniform
             const float wsum = separable_weight_sum<KMAX>(wa, wb);
             if (wsum > 0.0f) {

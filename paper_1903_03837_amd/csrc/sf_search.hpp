@@ -388,7 +388,7 @@ __device__ __forceinline__ int slot_index(int c, uint32_t t, int f_km1, int f_k)
 // Selection over a first set, centred on c, assumed centred on its nearest
 // candidate.  Returns whether it is; best is the set's nearest candidate
 // either way.  out_idx and out_d2 hold the K nearest (out_d2 rounded down as
-// above for K <= 5) only when it returns true.
+// above) only when it returns true.
 template <int KMAX>
 __device__ __forceinline__ bool select_k_centred(const Cand9& C, const SfZone& Z, int c, int K, int* out_idx,
                                                  float* out_d2, int& best) {
@@ -431,21 +431,31 @@ __device__ __forceinline__ bool select_k_centred(const Cand9& C, const SfZone& Z
         }
         return centred;
     } else {
-        // all nine sorted on the 64-bit keys (select_k ignores centre_min here)
-        uint64_t key[9];
-        cand_keys(C, key);
+        // all nine sorted by nine rounds of odd-even transposition; the set
+        // is centred when its smallest key is the centre's (slot 0)
+        uint32_t key[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) key[t] = slot_key(C.d2[t], t);
 #pragma unroll
         for (int p = 0; p < 9; ++p)
 #pragma unroll
             for (int a = (p & 1); a + 1 < 9; a += 2) {
-                const uint64_t lo = key[a] < key[a + 1] ? key[a] : key[a + 1];
-                const uint64_t hi = key[a] < key[a + 1] ? key[a + 1] : key[a];
+                const uint32_t lo = min(key[a], key[a + 1]), hi = max(key[a], key[a + 1]);
                 key[a] = lo;
                 key[a + 1] = hi;
             }
-        best = (int)(uint32_t)key[0];
-        keys_out<KMAX>(key, K, out_idx, out_d2);
-        return best == C.idx[0];
+        const int f_km1 = Z.f_km1, f_k = Z.f_k;
+        int id[KMAX];
+#pragma unroll
+        for (int r = 0; r < KMAX; ++r) id[r] = slot_index(c, key[r] & 15u, f_km1, f_k);
+        best = id[0];
+#pragma unroll
+        for (int r = 0; r < KMAX; ++r) {
+            const bool ok = r < K && key[r] < kInvalidKey;
+            out_idx[r] = ok ? id[r] : -1;
+            out_d2[r] = __uint_as_float(key[r] & ~15u);
+        }
+        return (key[0] & 15u) == 0u;
     }
 }
 
