@@ -462,8 +462,17 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
         }
     }
     // K = 9 lists alone fill a dictionary: only the per-pair path below
-    if constexpr (KMAX < kDict)
+    if constexpr (KMAX < kDict) {
         if (mfma_scatter<KMAX>(P, L, live, ia, wa, jb, wb, inv, gi)) return;
+        // The wave's texels overflow a dictionary: each half of its tile (8 x 4
+        // pixels, with fewer distinct neighbours) on its own; only a half
+        // that still overflows (or a non-finite adjoint) takes the per-pair
+        // path.
+        const bool low = (threadIdx.x & 63) < 32;
+        if (mfma_scatter<KMAX>(P, L, live && low, ia, wa, jb, wb, inv, gi)) live = live && !low;
+        if (mfma_scatter<KMAX>(P, L, live && !low, ia, wa, jb, wb, inv, gi)) live = live && low;
+        if (__ballot(live) == 0) return;
+    }
 #pragma unroll
     for (int a = 0; a < KMAX; ++a)
 #pragma unroll
@@ -478,10 +487,11 @@ __device__ __forceinline__ void lookup_adjoint_pixel(const LookupParams& P, Scat
 }
 
 // Adjoint (and the fused L2 variant): every lane of the wave takes part in
-// the aggregated scatter (no early exit).  8 waves per SIMD (64 VGPRs, a few values spilled) ran 3 %
-// faster than 7 waves with no spills.
+// the aggregated scatter (no early exit).  K <= 5: 8 waves per SIMD (64
+// VGPRs, a few values spilled) ran 3 % faster than 7 waves with no spills;
+// K = 9 (per-pair scatter of 81 pairs) is held to 3, where it has no spills.
 template <int KMAX, int DT, bool L2>
-__global__ __launch_bounds__(256, 8) void lookup_adjoint_kernel(LookupParams P) {
+__global__ __launch_bounds__(256, KMAX <= 5 ? 8 : 3) void lookup_adjoint_kernel(LookupParams P) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ ScatterLds lds[4];
     const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
