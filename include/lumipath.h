@@ -178,9 +178,10 @@ int lf_version(void);
  *   xyz_out: NULL or float [n][3], p_i for i < n (frac(i/Phi) in FP64).
  *   query:   NULL or float [nq][3] unit vectors; then idx_out int32 [nq][K]
  *            receives the K nearest of the candidate set i* + {0, +-F(k-1),
- *            +-F(k), +-F(k+1), +-F(k+2)} in order of distance (squared
- *            distances compared to 20 significant bits, ties by candidate
- *            slot), -1 where fewer exist, and w_out (may be NULL) float
+ *            +-F(k), +-F(k+1), +-F(k+2)} in order of distance (on the
+ *            first candidate set, squared distances compared to 20
+ *            significant bits, ties by candidate slot; after a descent, by
+ *            (distance, index)), -1 where fewer exist, and w_out (may be NULL) float
  *            [nq][K] the tent weights max(0, 1 - d / sqrt(4 pi / n)) (d:
  *            unit chord).
  *            idx_out[q][0] is the nearest point.  1 <= K <= 9.
