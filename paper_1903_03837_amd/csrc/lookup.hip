@@ -10,10 +10,12 @@
 // blend.  The adjoint sums each wave's contributions before its atomics:
 // as a dense contraction over the wave's 64 pixels on MFMA when the wave's
 // distinct origin and direction neighbours fit dictionaries of 8 (most
-// waves at view resolution), otherwise per pair slot after sorting each
+// waves at view resolution), else over each half of the wave's tile, and
+// for a half that still overflows per pair slot after sorting each
 // pixel's neighbour lists by index (neighbouring pixels then hold equal
 // texels in equal slots, which are summed across the wave with DPP).  One
-// float atomic per channel is issued per distinct texel either way.
+// float atomic per channel is issued per distinct texel of each
+// contraction or pair slot.
 #include <hip/hip_fp16.h>
 
 #include <mutex>
