@@ -430,7 +430,16 @@ __global__ __launch_bounds__(256, WAVES) void gen_wave_kernel(TraceParams P) {
                 GridWalk gw;
                 gw.init(P, x, sd, isd, t);
                 float sbA = 0.0f, sbB = 0.0f, tA, tB;
+                // The walk is a chain of dependent steps (an LDS read of the
+                // cell's majorant, then ~40 instructions) that the wave's
+                // slowest lane drags out; raised wave priority lets it issue
+                // ahead of the other waves of its SIMD, whose volume loads are
+                // in flight meanwhile.  Scheduling only: the same instructions
+                // and results.  Measured in the forward modes (1.4 % faster at
+                // N = 32768, 1.7 % at N = 8192); the adjoint keeps the default.
+                if constexpr (MODE != kGrad) __builtin_amdgcn_s_setprio(2);
                 gw.next2(P, mg, stepA, neg_log1m(u01(r.x)), neg_log1m(u01(r.z)), tend, tA, sbA, tB, sbB, cnt.cells);
+                if constexpr (MODE != kGrad) __builtin_amdgcn_s_setprio(0);
                 const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
                 const float rawA = sample_volume<VT>(P, yA);
                 const float rawB = sample_volume<VT>(P, yB);
