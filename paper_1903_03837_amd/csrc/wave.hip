@@ -434,15 +434,20 @@ __global__ __launch_bounds__(256, WAVES) void gen_wave_kernel(TraceParams P) {
                 // cell's majorant, then ~40 instructions) that the wave's
                 // slowest lane drags out; raised wave priority lets it issue
                 // ahead of the other waves of its SIMD, whose volume loads are
-                // in flight meanwhile.  Scheduling only: the same instructions
-                // and results.  Measured in the forward modes (1.4 % faster at
-                // N = 32768, 1.7 % at N = 8192); the adjoint keeps the default.
+                // in flight meanwhile.  With 3 waves per SIMD (the HBM-bound
+                // budget) the volume fetch that follows runs at that priority
+                // too; with 4 it must not (20 % slower).  Scheduling only:
+                // the same instructions and results.  Measured in the forward
+                // modes (N = 32768 at 3 waves 4524 -> 4465 -> 4370 ms, N = 8192
+                // at 4 waves 741 -> 729 ms); the adjoint keeps the default.
                 if constexpr (MODE != kGrad) __builtin_amdgcn_s_setprio(2);
                 gw.next2(P, mg, stepA, neg_log1m(u01(r.x)), neg_log1m(u01(r.z)), tend, tA, sbA, tB, sbB, cnt.cells);
                 if constexpr (MODE != kGrad) __builtin_amdgcn_s_setprio(0);
                 const f3 yA = fma3(sd, tA, x), yB = fma3(sd, tB, x);
+                if constexpr (MODE != kGrad && WAVES == 3) __builtin_amdgcn_s_setprio(2);
                 const float rawA = sample_volume<VT>(P, yA);
                 const float rawB = sample_volume<VT>(P, yB);
+                if constexpr (MODE != kGrad && WAVES == 3) __builtin_amdgcn_s_setprio(0);
                 bool more = true;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
